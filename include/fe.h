@@ -1,0 +1,279 @@
+/*
+ * fe.h -- C ABI of the MI355X implicit finite-element step library.
+ *
+ * The library implements the per-time-step hot path of the implicit FE
+ * method of Zeng & Courtecuisse, "Efficient parallelization strategy for
+ * real-time FE simulations" (arXiv 2306.05893):
+ *
+ *   assembly   element tangents and internal forces, scattered through a map
+ *              built once from the topology into a fixed-pattern CSR matrix
+ *              A = (1 + h alpha) M + h (beta + h) K and right-hand side b
+ *              (Sec. 3.2, Eq. "dynamic equation2"; Sec. 4.2 "fast assembly");
+ *   solve      preconditioned CG on A whose preconditioner is the LDL^T
+ *              factor of an earlier A (Sec. 3.3, Eq. "asynchronous
+ *              preconditioner"), applied by level-scheduled triangular solves
+ *              over a nested-dissection partition (Sec. 5.1, Eq. "regional
+ *              problem");
+ *   step       backward-Euler update (Eq. "implicit integration").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int: FE_OK (0) or a negative FE_E* code.  No
+ *   C++ exception crosses this boundary.  fe_last_error(ctx) returns a
+ *   human-readable message for the last failing call on that context.
+ * - "host" pointers point to CPU memory, "device" pointers to GPU memory
+ *   (hipMalloc'd or a torch CUDA tensor).  Device buffers passed to a call
+ *   are owned by the caller and must stay valid until the work queued on
+ *   `stream` has completed.  The library allocates no device memory of its
+ *   own: fe_query reports how many bytes of device workspace a context needs
+ *   and fe_bind hands it a caller-owned buffer of that size.
+ * - DOF numbering: DOF 3*i + c is coordinate c of node i.  All state and
+ *   force vectors are FP64, length 3*n_nodes.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Calls on one context are not re-entrant; use one context per stream.
+ * - Precision: FE_PREC_FP64 computes everything in FP64.  FE_PREC_MIXED
+ *   stores A and the factor panels in FP32 and runs element arithmetic, the
+ *   SpMV products and the triangular solves in FP32, while state, CG vectors,
+ *   dot products, alpha/beta, the SpMV row sums and the residual check stay
+ *   FP64; the LDL^T factorisation itself is always FP64 on the host.
+ */
+#ifndef FE_H
+#define FE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define FE_OK         0
+#define FE_EINVAL    -1  /* bad argument, index or size                        */
+#define FE_ENOMEM    -2  /* host allocation failed / workspace too small       */
+#define FE_EINVERTED -3  /* an element has det F <= 0 (inverted)               */
+#define FE_EINDEF    -4  /* CG breakdown: p^T A p <= 0 (A not SPD)             */
+#define FE_ENOTCONV  -5  /* CG hit max_it; x and the stats are still valid     */
+#define FE_EFACTOR   -6  /* LDL^T hit a non-positive pivot                     */
+#define FE_EBUSY     -7  /* a factorisation job is still running               */
+#define FE_EDEVICE   -8  /* a HIP runtime call failed                          */
+#define FE_ESTATE    -9  /* call out of order (e.g. not bound yet)             */
+
+/* ---- enumerations ------------------------------------------------------ */
+#define FE_TET4 4               /* linear tetrahedron, 1 quadrature point    */
+#define FE_HEX8 8               /* trilinear hexahedron, 2x2x2 Gauss points  */
+
+#define FE_NEO_HOOKEAN 0        /* compressible neo-Hookean                  */
+#define FE_STVK        1        /* St Venant-Kirchhoff                       */
+
+#define FE_PREC_FP64  0
+#define FE_PREC_MIXED 1
+
+#define FE_FACTOR_DETERMINISTIC 0 /* factor of A_{kR} used from step kR+d   */
+#define FE_FACTOR_ASYNC         1 /* newest finished factor is swapped in    */
+
+typedef struct fe_ctx fe_ctx;
+
+/* Mesh topology and rest geometry (host arrays, read during the call). */
+typedef struct {
+  int32_t n_nodes;
+  int32_t n_elems;
+  int32_t elem_type;          /* FE_TET4 or FE_HEX8                           */
+  const int32_t *conn;        /* host [n_elems * nen], element-major          */
+  const double *X;            /* host [3 * n_nodes] rest coordinates          */
+} fe_mesh;
+
+typedef struct {
+  int32_t leaf_nodes;         /* nested-dissection leaf size in nodes (0: 48) */
+  int32_t n_threads;          /* host factorisation threads (0: all cores)    */
+} fe_build_opts;
+
+/* Physical parameters of one assembly.  E and f_nodal are DEVICE pointers. */
+typedef struct {
+  double h;                   /* time step                                    */
+  double alpha, beta;         /* Rayleigh damping B = alpha M + beta K        */
+  double rho;                 /* density                                      */
+  double nu;                  /* Poisson ratio                                */
+  int32_t material;           /* FE_NEO_HOOKEAN or FE_STVK                    */
+  int32_t pad_;
+  double gravity[3];          /* body acceleration                            */
+  const double *E;            /* device [n_elems] Young's modulus per element */
+  const double *f_nodal;      /* device [3 n_nodes] point loads, or NULL      */
+} fe_params;
+
+typedef struct {
+  int64_t n_dofs;             /* 3 * n_nodes                                  */
+  int64_t nnz;                /* CSR nonzeros of A (structural)               */
+  int64_t n_elems;
+  int64_t map_len;            /* canonical map entries = n_elems * (3 nen)^2  */
+  int64_t n_supernodes;       /* nested-dissection blocks of the factor       */
+  int64_t n_levels;           /* dependency levels of the triangular solves   */
+  int64_t factor_entries;     /* stored panel entries (incl. explicit zeros)  */
+  int64_t factor_lower;       /* panel entries on/below the diagonal          */
+  double factor_flops;        /* flops of one numeric factorisation           */
+  int64_t ws_bytes;           /* device workspace for the queried precision   */
+  int32_t compact_map;        /* 1: 1-byte slot map in use, 0: int32 map      */
+  int32_t pad_;
+} fe_sizes;
+
+typedef struct {
+  int32_t iterations;         /* CG iterations performed                      */
+  int32_t status;             /* FE_OK / FE_ENOTCONV / FE_EINDEF              */
+  double rel_res;             /* FP64 recomputed ||b - A x|| / ||b||          */
+  int64_t factor_tag;         /* tag of the factor used, -1 = Jacobi          */
+} fe_solve_stats;
+
+typedef struct {
+  double rel_tol;             /* stopping test on the recomputed residual     */
+  int32_t max_it;
+  int32_t refresh;            /* R: factor A every R steps (0: never)         */
+  int32_t lag;                /* d: deterministic mode uses A_{kR} from kR+d  */
+  int32_t mode;               /* FE_FACTOR_DETERMINISTIC / FE_FACTOR_ASYNC    */
+  int32_t warm_start;         /* 1: start CG from the previous acceleration   */
+  int32_t pad_;
+} fe_step_opts;
+
+typedef struct {
+  fe_solve_stats solve;
+  int64_t step;               /* index of the step just taken                 */
+  int64_t factor_lag;         /* step - tag of the factor used (-1: Jacobi)   */
+} fe_step_stats;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Build the CSR pattern of A and the element-to-nonzero map by two counting
+ * sort transposes of the triplet keys, dropping the rows/columns of fixed
+ * DOFs and giving them a lone diagonal entry (Sec. 4.2, Table "build
+ * pattern"; Sec. 6.1).  Also computes the nested-dissection ordering, the
+ * supernodal structure of L and the level sets of the triangular solves
+ * (Sec. 5.1).  Host work only; no GPU is touched.
+ *   mesh       topology and rest coordinates (host)
+ *   fixed_dof  host [3 n_nodes], 1 = Dirichlet DOF, NULL = none
+ *   opts       NULL for defaults
+ *   out        receives a new context (free with fe_destroy)
+ * Errors: FE_EINVAL (node index out of range, bad element type, an element
+ * with non-positive rest volume), FE_ENOMEM. */
+int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof,
+                     const fe_build_opts *opts, fe_ctx **out);
+
+/* Sizes of the context's structures; ws_bytes is for precision `prec`. */
+int fe_query(fe_ctx *ctx, int32_t prec, fe_sizes *out);
+
+/* Bind a caller-owned device workspace of at least fe_query().ws_bytes bytes
+ * (256-byte aligned) for precision `prec`, upload the pattern, map, mesh and
+ * solve schedule into it (queued on `stream`), and start the factor thread.
+ * Errors: FE_ENOMEM (buffer too small), FE_EINVAL, FE_EDEVICE. */
+int fe_bind(fe_ctx *ctx, int32_t prec, void *d_workspace, int64_t ws_bytes,
+            void *stream);
+
+/* Copy the pattern and the canonical triplet map to host arrays:
+ *   row_ptr [n_dofs + 1], col_idx [nnz], map [map_len] (triplet t of the
+ *   element-major fill order -> CSR slot, -1 = dropped).  Any pointer may be
+ *   NULL.  Host work only. */
+int fe_export_pattern(fe_ctx *ctx, int32_t *row_ptr, int32_t *col_idx, int32_t *map);
+
+/* Export the nested-dissection permutation (host [n_dofs]: perm[k] = DOF
+ * eliminated k-th; fixed DOFs last) and the supernode boundaries
+ * (host [n_supernodes + 1] offsets into perm).  Either pointer may be NULL. */
+int fe_export_ordering(fe_ctx *ctx, int32_t *perm, int32_t *sn_ptr);
+
+/* Assemble A (CSR values, FP32 for FE_PREC_MIXED / FP64 for FE_PREC_FP64,
+ * device [nnz]) and b (FP64 device [n_dofs]) at state (q, v) (device [n_dofs]
+ * each):  A = (1 + h alpha) M + h (beta + h) K(q),
+ *         b = p - f(q) - alpha M v - (beta + h) K(q) v,   p = M g + f_nodal,
+ * with fixed rows/cols replaced by the identity and b_d = 0 (Sec. 3.2,
+ * Sec. 4.2 merged LHS/RHS assembly, Sec. 6.1).  Queued on `stream`; returns
+ * FE_EINVERTED if an element with det F <= 0 was met (checked after the
+ * stream work completes, so this call synchronises `stream`). */
+int fe_assemble(fe_ctx *ctx, const fe_params *params, const double *q,
+                const double *v, void *A_vals, double *b, void *stream);
+
+/* Snapshot A (device, the context's precision) after the work queued on
+ * `stream`, and factor it as P = L D L^T in FP64 on the host factor thread
+ * (Sec. 3.3).  Returns at once.  `tag` labels the factor (usually the step
+ * index).  FE_EBUSY if a previous job has not finished. */
+int fe_factor_async(fe_ctx *ctx, const void *A_vals, int64_t tag, void *stream);
+
+/* Newest finished factor's tag (-1 if none) and the status of the last job. */
+int fe_factor_status(fe_ctx *ctx, int64_t *ready_tag);
+
+/* Block until the job with `tag` has finished; returns its status. */
+int fe_factor_wait(fe_ctx *ctx, int64_t tag);
+
+/* Make the newest finished factor the preconditioner for later solves (the
+ * upload is queued on an internal copy stream and ordered before later work
+ * on `stream`).  Returns its tag in *tag (NULL allowed), -1 if none. */
+int fe_factor_install(fe_ctx *ctx, int64_t *tag, void *stream);
+
+/* Preconditioned CG on A x = b (Sec. 5, Fig. "DataTransfer": SpMV, vector
+ * operations and the preconditioner all on the GPU, one small status word
+ * read back per batch of iterations).  A_vals device [nnz] in the context's
+ * precision, b and x FP64 device [n_dofs]; x holds x0 on entry.  Stops when
+ * the FP64 recomputed ||b - A x|| <= rel_tol ||b||.  Preconditioner: the
+ * installed LDL^T factor, else Jacobi.  Synchronises `stream`.
+ * Errors: FE_ENOTCONV (x, stats valid), FE_EINDEF. */
+int fe_pcg_solve(fe_ctx *ctx, const void *A_vals, const double *b, double *x,
+                 double rel_tol, int32_t max_it, void *stream, fe_solve_stats *stats);
+
+/* One full step at state (q, v) (device, FP64, updated in place): assemble,
+ * schedule/install factors per opts, solve A a = b, then v += h a,
+ * q += h v (Eq. "implicit integration").  a_out (device [n_dofs]) may be
+ * NULL.  A, b and the CG vectors live in the workspace. */
+int fe_step(fe_ctx *ctx, double *q, double *v, const fe_params *params,
+            const fe_step_opts *opts, double *a_out, void *stream, fe_step_stats *stats);
+
+/* One reverse step of the adjoint of fe_step (not in the paper).  Given the
+ * state (q_n, v_n) of the forward step, its output velocity v_np1 and the
+ * incoming adjoints lam_q_in = dL/dq_{n+1}, lam_v_in = dL/dv_{n+1}:
+ *   abar = h lam_v_in + h^2 lam_q_in (fixed DOFs 0);  A mu = abar (same PCG);
+ *   lam_v_out = lam_v_in + h lam_q_in - alpha M mu - (beta + h) K mu
+ *   lam_q_out = lam_q_in - K mu - (beta + h) T(q_n)[mu, v_np1]
+ *   dE_accum[e] += -(mu_e . f_e + (beta + h) mu_e . K_e v_np1_e) / E_e
+ * with T the directional derivative of K.  All vectors FP64 device.
+ * The lam_*_out buffers may alias lam_*_in. */
+int fe_step_adjoint(fe_ctx *ctx, const double *q_n, const double *v_n,
+                    const double *v_np1, const double *lam_q_in, const double *lam_v_in,
+                    double *lam_q_out, double *lam_v_out, double *dE_accum,
+                    const fe_params *params, const fe_step_opts *opts, void *stream,
+                    fe_solve_stats *stats);
+
+/* y = A x (A device [nnz] in the context's precision, x, y FP64 device). */
+int fe_spmv(fe_ctx *ctx, const void *A_vals, const double *x, double *y, void *stream);
+
+/* z = P^{-1} r with the installed factor (Jacobi on A_vals if none). */
+int fe_precond_apply(fe_ctx *ctx, const void *A_vals, const double *r, double *z,
+                     void *stream);
+
+/* Host-only check of the factorisation (no GPU): factor the FP64 CSR values
+ * A_host (host [nnz]) with the context's ordering and supernodes, then apply
+ * z = P^{-1} r on the host with the same explicit-inverse panels and the same
+ * forward / diagonal / backward order as the GPU sweeps, for n_rhs
+ * right-hand sides stored one after another in r_host / z_host
+ * (host [n_rhs * n_dofs]).  Errors: FE_EFACTOR (non-positive pivot). */
+int fe_host_factor_apply(fe_ctx *ctx, const double *A_host, const double *r_host,
+                         double *z_host, int32_t n_rhs);
+
+/* Per-kernel timing: when enabled, the library brackets every launch of the
+ * triangular-solve and SpMV kernels with HIP events on the launch stream and
+ * accumulates their durations; fe_kernel_times reads and resets them.
+ *   names: 0 spmv, 1 trisolve forward, 2 trisolve backward, 3 element
+ *   out_ms[k], out_count[k], out_bytes[k] (algorithmic bytes moved). */
+int fe_set_kernel_timing(fe_ctx *ctx, int32_t enable);
+int fe_kernel_times(fe_ctx *ctx, double *out_ms, int64_t *out_count, double *out_bytes,
+                    int32_t n);
+
+/* Reset the step counter and drop installed factors (new rollout). */
+int fe_reset(fe_ctx *ctx);
+
+/* Join the factor thread and free all host state.  NULL is a no-op. */
+int fe_destroy(fe_ctx *ctx);
+
+/* Message of the last error on ctx (or of the last failed fe_build_pattern
+ * when ctx is NULL).  Valid until the next call on ctx. */
+const char *fe_last_error(fe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FE_H */

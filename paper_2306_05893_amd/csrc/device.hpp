@@ -1,0 +1,119 @@
+// Device-side structures and kernel launchers of the FE step library
+// (HIP for gfx950).  Shared by kernels_*.hip and the C-ABI implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fe {
+
+struct SnDev {          // one supernode of the factor, as the GPU sees it
+  int32_t nc, m;        // own columns, panel rows
+  int64_t panel_off;    // entry offset of the m x nc column-major panel
+  int64_t rows_off;     // offset into the rows array (DOF indices)
+};
+
+struct TileDev {
+  int32_t s, r0, c0, pad;
+};
+
+// Control block of one CG solve (device memory, read back by the host).
+struct PcgState {
+  double rz;            // r . z of the current iterate
+  double pAp;
+  double rr;            // ||r||^2 (recursive)
+  double bb;            // ||b||^2
+  double alpha, beta;
+  double tol2;          // rel_tol^2 * ||b||^2
+  double rr_true;       // recomputed ||b - A x||^2
+  int32_t it;           // iterations done
+  int32_t done;         // 1: converged candidate / breakdown -> kernels no-op
+  int32_t status;       // 0 ok, 4 = p^T A p <= 0
+  int32_t elem_status;  // bit 0: an element had det F <= 0 or det J <= 0
+};
+
+struct ElemParams {
+  double h, alpha, beta, rho, nu;
+  double gx, gy, gz;
+  int32_t material;     // 0 neo-Hookean, 1 StVK
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- launchers
+// Assembly: A <- 0 with fixed diagonals 1; b <- f_nodal (0 on fixed DOFs).
+template <typename T>
+void launch_assembly_init(hipStream_t st, int64_t nnz, T *A, int64_t n_fixed,
+                          const int32_t *fixed_diag_slot, int64_t n, double *b,
+                          const double *f_nodal, const uint8_t *dof_fixed);
+
+// Element tangents + forces, scattered into A (CSR) and b.
+//   slot: compact map [E][nen*nen] (1 byte) or NULL with smap [E][(3nen)^2]
+template <typename T>
+void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_t *conn,
+                    const uint8_t *slot, const int32_t *smap, const int32_t *row_ptr,
+                    const double *X, const double *q, const double *v, const double *E,
+                    const uint8_t *dof_fixed, const ElemParams &prm, T *A, double *b,
+                    PcgState *state);
+
+// y = A x; if dot_partial != NULL also sum_i w[i] y[i] per block.
+template <typename T>
+void launch_spmv(hipStream_t st, int64_t n, int rows_per_lanes, const int32_t *row_ptr,
+                 const int32_t *col, const T *val, const double *x, double *y,
+                 const double *w, double *dot_partial, int *n_partial, const PcgState *state);
+int spmv_lanes_for(double avg_row_nnz);
+
+// Triangular sweeps z = P^{-1} r with P = L D L^T in explicit-inverse panels.
+template <typename T>
+void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, double *z,
+                     const uint8_t *dof_fixed, const PcgState *state);
+template <typename T>
+void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state);
+template <typename T>
+void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+                    const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
+                    const PcgState *state);
+
+// Jacobi: dinv_A[i] = 1 / A_ii ; z = dinv_A * r
+template <typename T>
+void launch_diag_inv(hipStream_t st, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                     const T *val, double *dinv);
+void launch_jacobi(hipStream_t st, int64_t n, const double *dinv, const double *r, double *z,
+                   const PcgState *state);
+
+// CG vector kernels (all no-ops once state->done is set).
+int cg_blocks(int64_t n);
+void launch_residual(hipStream_t st, int64_t n, const double *b, const double *Ax, double *r,
+                     double *part_rr, double *part_bb);
+void launch_ctl_init(hipStream_t st, PcgState *s, const double *part_rr, const double *part_bb,
+                     int np, double rel_tol);
+void launch_dot(hipStream_t st, int64_t n, const double *a, const double *b, double *part,
+                const PcgState *state);
+void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int first);
+void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np);
+void launch_update_xr(hipStream_t st, int64_t n, double *x, double *r, const double *p,
+                      const double *q, double *part_rr, const PcgState *state);
+void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np);
+void launch_update_p(hipStream_t st, int64_t n, double *p, const double *z, const PcgState *state,
+                     int first);
+void launch_ctl_true(hipStream_t st, PcgState *s, const double *part, int np);
+void launch_zero(hipStream_t st, int64_t n, double *x);
+void launch_integrate(hipStream_t st, int64_t n, double h, const double *a, double *q,
+                      double *v);
+
+// Adjoint element pass: lam_q_out, lam_v_out, dE (see fe.h fe_step_adjoint)
+template <typename T>
+void launch_adjoint_element(hipStream_t st, int elem_type, int64_t n_elems,
+                            const int32_t *conn, const double *X, const double *q,
+                            const double *mu, const double *vnp1, const double *E,
+                            const ElemParams &prm, double *Kmu, double *Mmu, double *Tmv,
+                            double *dE);
+void launch_adjoint_combine(hipStream_t st, int64_t n, double h, double alpha, double beta,
+                            const double *lq_in, const double *lv_in, const double *Kmu,
+                            const double *Mmu, const double *Tmv, double *lq_out,
+                            double *lv_out);
+void launch_abar(hipStream_t st, int64_t n, double h, const double *lq, const double *lv,
+                 const uint8_t *dof_fixed, double *abar);
+
+}  // namespace fe

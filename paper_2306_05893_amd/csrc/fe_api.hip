@@ -1,0 +1,1087 @@
+// C-ABI entry points of the FE step library (declared in include/fe.h).
+//
+// Structure of one context:
+//   host:    pattern + map (two counting-sort transposes), nested-dissection
+//            ordering, supernodal symbolic structure and tile schedules;
+//            a factor thread that runs the FP64 LDL^T of a snapshot of A
+//            (paper Sec. 3.3, asynchronous preconditioner);
+//   device:  one caller-owned workspace holding the topology, two factor
+//            slots (double buffering: one in use by the solves, the other
+//            receiving the next upload on a copy stream), CG vectors and the
+//            control block that the kernels read to stop early.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fe.h"
+#include "device.hpp"
+#include "host.hpp"
+
+using namespace fe;
+
+namespace {
+
+thread_local std::string g_build_error;
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      return c->fail(FE_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    }                                                                                   \
+  } while (0)
+
+struct Timing {
+  int kind;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct fe_ctx {
+  std::string err;
+  Pattern P;
+  Symbolic S;
+  std::vector<double> X;
+  int elem_type = 0, nen = 0, n_threads = 0;
+  int spmv_lanes = 8;
+
+  // ---- binding
+  bool bound = false;
+  int prec = FE_PREC_FP64;
+  int device = 0;
+  size_t tsize = 8;
+  char *ws = nullptr;
+  int64_t ws_bytes = 0;
+  int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_conn = nullptr, *d_smap = nullptr,
+          *d_fds = nullptr, *d_rows = nullptr;
+  uint8_t *d_slot = nullptr, *d_dof_fixed = nullptr;
+  double *d_X = nullptr;
+  SnDev *d_sn = nullptr;
+  TileDev *d_ftiles = nullptr, *d_btiles = nullptr;
+  void *d_panels[2] = {nullptr, nullptr}, *d_dinv[2] = {nullptr, nullptr};
+  double *d_jdinv = nullptr;
+  double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_tmp = nullptr;
+  double *d_b = nullptr, *d_a = nullptr, *d_abar = nullptr, *d_mu = nullptr;
+  double *d_Kmu = nullptr, *d_Mmu = nullptr, *d_Tmv = nullptr;
+  void *d_w = nullptr, *d_y = nullptr, *d_A = nullptr;
+  double *d_part1 = nullptr, *d_part2 = nullptr;
+  PcgState *d_state = nullptr;
+
+  // ---- host-side HIP resources
+  PcgState *h_state = nullptr;
+  void *h_Asnap = nullptr;
+  void *h_stage = nullptr;   // panels (T) followed by dinv (T)
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t ev_snap_ready = nullptr, ev_snap_done = nullptr, ev_upload_done = nullptr;
+  hipEvent_t ev_slot_free[2] = {nullptr, nullptr};
+  bool upload_issued = false;
+
+  // ---- factor thread
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  bool quit = false, job_pending = false, job_running = false;
+  int64_t job_tag = -1, ready_tag = -1;
+  int job_status = FE_OK;
+  std::string job_err;
+  double last_factor_seconds = 0.0;
+  int active_slot = -1;
+  int64_t installed_tag = -1;
+  int64_t step_count = 0;
+  bool have_prev_a = false;
+
+  // ---- timing
+  bool timing = false;
+  std::vector<Timing> tq;
+  std::vector<hipEvent_t> ev_pool;
+  double t_ms[4] = {0, 0, 0, 0}, t_bytes[4] = {0, 0, 0, 0};
+  int64_t t_count[4] = {0, 0, 0, 0};
+  std::vector<double> fwd_level_bytes, bwd_level_bytes;
+
+  int fail(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    return code;
+  }
+  ~fe_ctx();
+};
+
+namespace {
+
+// ------------------------------------------------------------- layout
+struct Layout {
+  int64_t off[40];
+  int64_t total = 0;
+  int k = 0;
+  int64_t add(int64_t bytes) {
+    const int64_t o = total;
+    off[k++] = o;
+    total += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+enum {
+  L_ROWPTR, L_COL, L_CONN, L_SLOT, L_SMAP, L_FDS, L_DOFFIX, L_X, L_SN, L_ROWS, L_FT, L_BT,
+  L_PAN0, L_PAN1, L_DINV0, L_DINV1, L_JDINV, L_R, L_Z, L_P, L_Q, L_TMP, L_B, L_ACC, L_ABAR,
+  L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE
+};
+
+Layout make_layout(const fe_ctx *c, int prec) {
+  const Pattern &P = c->P;
+  const Symbolic &S = c->S;
+  const int64_t ts = prec == FE_PREC_MIXED ? 4 : 8;
+  const int64_t n = P.n, nnz = (int64_t)P.col_idx.size();
+  const int64_t np = cg_blocks(n) + 16;
+  const int64_t spmv_parts = (n * c->spmv_lanes + 255) / 256 + 16;
+  Layout L;
+  L.add((n + 1) * 4);
+  L.add(nnz * 4);
+  L.add((int64_t)P.conn.size() * 4);
+  L.add(P.compact_ok ? (int64_t)P.slot.size() : 0);
+  L.add(P.compact_ok ? 0 : (int64_t)P.tmap.size() * 4);
+  L.add((int64_t)P.fixed_diag_slot.size() * 4);
+  L.add(n);
+  L.add(n * 8);
+  L.add((int64_t)S.sn.size() * (int64_t)sizeof(SnDev));
+  L.add((int64_t)S.rows.size() * 4);
+  L.add((int64_t)S.fwd_tiles.size() * (int64_t)sizeof(TileDev));
+  L.add((int64_t)S.bwd_tiles.size() * (int64_t)sizeof(TileDev));
+  L.add(S.panel_entries * ts);
+  L.add(S.panel_entries * ts);
+  L.add(n * ts);
+  L.add(n * ts);
+  L.add(n * 8);  // jdinv
+  for (int i = 0; i < 12; ++i) L.add(n * 8);  // r z p q tmp b a abar mu Kmu Mmu Tmv
+  L.add(n * ts);  // w
+  L.add(n * ts);  // y
+  L.add(nnz * ts);
+  L.add(std::max(np, spmv_parts) * 8);
+  L.add(std::max(np, spmv_parts) * 8);
+  L.add(256);
+  return L;
+}
+
+template <typename T>
+T *ptr_at(char *ws, const Layout &L, int k) {
+  return reinterpret_cast<T *>(ws + L.off[k]);
+}
+
+ElemParams to_elem(const fe_params *p) {
+  ElemParams e;
+  e.h = p->h;
+  e.alpha = p->alpha;
+  e.beta = p->beta;
+  e.rho = p->rho;
+  e.nu = p->nu;
+  e.gx = p->gravity[0];
+  e.gy = p->gravity[1];
+  e.gz = p->gravity[2];
+  e.material = p->material;
+  e.pad = 0;
+  return e;
+}
+
+// ------------------------------------------------------------- timing
+hipEvent_t take_event(fe_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void drain_timing(fe_ctx *c) {
+  for (auto &t : c->tq) {
+    (void)hipEventSynchronize(t.b);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      c->t_ms[t.kind] += ms;
+      c->t_count[t.kind] += 1;
+      c->t_bytes[t.kind] += t.bytes;
+    }
+    c->ev_pool.push_back(t.a);
+    c->ev_pool.push_back(t.b);
+  }
+  c->tq.clear();
+}
+
+struct TimedLaunch {
+  fe_ctx *c;
+  hipStream_t st;
+  Timing t;
+  bool on;
+  TimedLaunch(fe_ctx *c_, hipStream_t s, int kind, double bytes) : c(c_), st(s), on(c_->timing) {
+    if (on) {
+      t.kind = kind;
+      t.bytes = bytes;
+      t.a = take_event(c);
+      t.b = take_event(c);
+      (void)hipEventRecord(t.a, st);
+    }
+  }
+  ~TimedLaunch() {
+    if (on) {
+      (void)hipEventRecord(t.b, st);
+      c->tq.push_back(t);
+      if (c->tq.size() > 4096) drain_timing(c);
+    }
+  }
+};
+
+// ------------------------------------------------------------- factor thread
+template <typename T>
+void stage_factor(fe_ctx *c, const std::vector<double> &panels, const std::vector<double> &dinv) {
+  T *dst = reinterpret_cast<T *>(c->h_stage);
+  const int64_t np = (int64_t)panels.size();
+  parallel_for(64, c->n_threads, [&](int64_t b, int) {
+    const int64_t lo = np * b / 64, hi = np * (b + 1) / 64;
+    for (int64_t i = lo; i < hi; ++i) dst[i] = (T)panels[i];
+  });
+  T *dd = dst + c->S.panel_entries;
+  for (size_t i = 0; i < dinv.size(); ++i) dd[i] = (T)dinv[i];
+}
+
+void factor_main(fe_ctx *c) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    int64_t tag;
+    {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv.wait(lk, [&] { return c->quit || c->job_pending; });
+      if (c->quit) return;
+      c->job_pending = false;
+      c->job_running = true;
+      tag = c->job_tag;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    std::string e;
+    std::vector<double> panels, dinv;
+    if (hipEventSynchronize(c->ev_snap_done) != hipSuccess) e = "snapshot copy failed";
+    if (e.empty()) {
+      if (c->prec == FE_PREC_MIXED)
+        e = factorize<float>(c->P, c->S, (const float *)c->h_Asnap, c->n_threads, panels, dinv);
+      else
+        e = factorize<double>(c->P, c->S, (const double *)c->h_Asnap, c->n_threads, panels, dinv);
+    }
+    std::unique_lock<std::mutex> lk(c->mu);
+    if (e.empty()) {
+      // the staging buffer may still be feeding the previous upload
+      if (c->upload_issued) (void)hipEventSynchronize(c->ev_upload_done);
+      if (c->prec == FE_PREC_MIXED) stage_factor<float>(c, panels, dinv);
+      else stage_factor<double>(c, panels, dinv);
+      c->ready_tag = tag;
+      c->job_status = FE_OK;
+      c->job_err.clear();
+    } else {
+      c->job_status = FE_EFACTOR;
+      c->job_err = e;
+    }
+    c->last_factor_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    c->job_running = false;
+    c->cv.notify_all();
+  }
+}
+
+// ------------------------------------------------------------- solve pieces
+template <typename T>
+void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, bool use_state) {
+  const int64_t n = c->P.n;
+  const PcgState *s = use_state ? c->d_state : nullptr;
+  if (c->active_slot < 0) {
+    launch_jacobi(st, n, c->d_jdinv, r, z, s);
+    return;
+  }
+  (void)A;
+  const int slot = c->active_slot;
+  const T *pan = (const T *)c->d_panels[slot];
+  const T *dinv = (const T *)c->d_dinv[slot];
+  T *w = (T *)c->d_w, *y = (T *)c->d_y;
+  launch_tri_prep<T>(st, n, r, w, y, z, c->d_dof_fixed, s);
+  const Symbolic &S = c->S;
+  for (int L = 0; L < S.n_levels; ++L) {
+    const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
+    TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
+    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_sn, c->d_rows, pan, w, y, s);
+  }
+  for (int L = 0; L < S.n_levels; ++L) {
+    const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
+    TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
+    launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s);
+  }
+}
+
+template <typename T>
+void spmv(fe_ctx *c, const T *A, const double *x, double *y, const double *w, double *part,
+          int *np, hipStream_t st, const PcgState *s) {
+  const double nnz = (double)c->P.col_idx.size(), n = (double)c->P.n;
+  TimedLaunch tl(c, st, 0, nnz * (sizeof(T) + 4) + (n + 1) * 4 + n * 8 * 2);
+  launch_spmv<T>(st, c->P.n, c->spmv_lanes, c->d_row_ptr, c->d_col, A, x, y, w, part, np, s);
+}
+
+int read_state(fe_ctx *c, hipStream_t st) {
+  {
+    hipError_t e1 = hipMemcpyAsync(c->h_state, c->d_state, sizeof(PcgState),
+                                   hipMemcpyDeviceToHost, st);
+    if (e1 != hipSuccess) return c->fail(FE_EDEVICE, "state copy: %s", hipGetErrorString(e1));
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (e2 != hipSuccess) return c->fail(FE_EDEVICE, "stream sync: %s", hipGetErrorString(e2));
+  }
+  return FE_OK;
+}
+
+template <typename T>
+int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_it,
+        hipStream_t st, fe_solve_stats *out) {
+  const int64_t n = c->P.n;
+  const int nb = cg_blocks(n);
+  int np = 0;
+  if (c->active_slot < 0) launch_diag_inv<T>(st, n, c->d_row_ptr, c->d_col, A, c->d_jdinv);
+  // r = b - A x
+  spmv<T>(c, A, x, c->d_tmp, nullptr, nullptr, nullptr, st, nullptr);
+  launch_residual(st, n, b, c->d_tmp, c->d_r, c->d_part1, c->d_part2);
+  launch_ctl_init(st, c->d_state, c->d_part1, c->d_part2, nb, tol);
+  auto restart = [&]() {
+    precond<T>(c, A, c->d_r, c->d_z, st, true);
+    launch_dot(st, n, c->d_r, c->d_z, c->d_part1, c->d_state);
+    launch_ctl_rz(st, c->d_state, c->d_part1, nb, 1);
+    launch_update_p(st, n, c->d_p, c->d_z, c->d_state, 1);
+  };
+  restart();
+  int chunk = 2;
+  int status = FE_OK;
+  int restarts = 0;
+  int32_t last_it = -1;
+  for (;;) {
+    for (int k = 0; k < chunk; ++k) {
+      spmv<T>(c, A, c->d_p, c->d_q, c->d_p, c->d_part1, &np, st, c->d_state);
+      launch_ctl_alpha(st, c->d_state, c->d_part1, np);
+      launch_update_xr(st, n, x, c->d_r, c->d_p, c->d_q, c->d_part2, c->d_state);
+      launch_ctl_rr(st, c->d_state, c->d_part2, nb);
+      precond<T>(c, A, c->d_r, c->d_z, st, true);
+      launch_dot(st, n, c->d_r, c->d_z, c->d_part1, c->d_state);
+      launch_ctl_rz(st, c->d_state, c->d_part1, nb, 0);
+      launch_update_p(st, n, c->d_p, c->d_z, c->d_state, 0);
+    }
+    {
+      hipError_t le = hipGetLastError();
+      if (le != hipSuccess) return c->fail(FE_EDEVICE, "kernel launch: %s", hipGetErrorString(le));
+    }
+    int rc = read_state(c, st);
+    if (rc) return rc;
+    const PcgState &h = *c->h_state;
+    if (!h.done && h.status == 0 && h.it == last_it)
+      return c->fail(FE_EDEVICE, "CG iteration counter did not advance");
+    last_it = h.it;
+    if (h.status == 4) {
+      status = FE_EINDEF;
+      break;
+    }
+    if (h.done) {
+      // certify with the recomputed FP64 residual
+      spmv<T>(c, A, x, c->d_tmp, nullptr, nullptr, nullptr, st, nullptr);
+      launch_residual(st, n, b, c->d_tmp, c->d_r, c->d_part1, nullptr);
+      launch_ctl_true(st, c->d_state, c->d_part1, nb);
+      rc = read_state(c, st);
+      if (rc) return rc;
+      if (c->h_state->rr_true <= c->h_state->tol2 || c->h_state->bb == 0.0) break;
+      if (++restarts > 50) {
+        status = FE_ENOTCONV;
+        break;
+      }
+      // residual replacement: continue from the true residual
+      c->h_state->done = 0;
+      hipError_t e = hipMemcpyAsync(&c->d_state->done, &c->h_state->done, sizeof(int32_t),
+                                    hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return c->fail(FE_EDEVICE, "state reset: %s", hipGetErrorString(e));
+      restart();
+      continue;
+    }
+    if (h.it >= max_it) {
+      status = FE_ENOTCONV;
+      spmv<T>(c, A, x, c->d_tmp, nullptr, nullptr, nullptr, st, nullptr);
+      launch_residual(st, n, b, c->d_tmp, c->d_r, c->d_part1, nullptr);
+      launch_ctl_true(st, c->d_state, c->d_part1, nb);
+      rc = read_state(c, st);
+      if (rc) return rc;
+      break;
+    }
+    chunk = std::min(16, std::max(2, chunk * 2));
+    chunk = std::min(chunk, max_it - h.it);
+    if (chunk <= 0) chunk = 1;
+  }
+  if (out) {
+    out->iterations = c->h_state->it;
+    out->status = status;
+    out->rel_res = c->h_state->bb > 0 ? std::sqrt(c->h_state->rr_true / c->h_state->bb) : 0.0;
+    out->factor_tag = c->active_slot >= 0 ? c->installed_tag : -1;
+  }
+  if (status == FE_EINDEF) return c->fail(FE_EINDEF, "CG breakdown: p^T A p <= 0");
+  if (status == FE_ENOTCONV)
+    return c->fail(FE_ENOTCONV, "CG did not converge in %d iterations", c->h_state->it);
+  return FE_OK;
+}
+
+template <typename T>
+int assemble(fe_ctx *c, const fe_params *p, const double *q, const double *v, T *A, double *b,
+             hipStream_t st) {
+  const ElemParams ep = to_elem(p);
+  launch_assembly_init<T>(st, (int64_t)c->P.col_idx.size(), A,
+                          (int64_t)c->P.fixed_diag_slot.size(), c->d_fds, c->P.n, b,
+                          p->f_nodal, c->d_dof_fixed);
+  const double bytes = (double)c->P.col_idx.size() * sizeof(T) + 8.0 * c->P.n +
+                       (4.0 * c->nen + 8.0 + (c->P.compact_ok ? c->nen * c->nen : 36.0 * c->nen * c->nen)) *
+                           c->P.n_elems + 72.0 * c->P.n_nodes;
+  TimedLaunch tl(c, st, 3, bytes);
+  launch_element<T>(st, c->elem_type, c->P.n_elems, c->d_conn,
+                    c->P.compact_ok ? c->d_slot : nullptr, c->P.compact_ok ? nullptr : c->d_smap,
+                    c->d_row_ptr, c->d_X, q, v, p->E, c->d_dof_fixed, ep, A, b, c->d_state);
+  return FE_OK;
+}
+
+int check_params(fe_ctx *c, const fe_params *p) {
+  if (!p) return c->fail(FE_EINVAL, "params is NULL");
+  if (!p->E) return c->fail(FE_EINVAL, "params->E is NULL");
+  if (p->material != FE_NEO_HOOKEAN && p->material != FE_STVK)
+    return c->fail(FE_EINVAL, "unknown material %d", p->material);
+  if (!(p->h > 0)) return c->fail(FE_EINVAL, "h must be positive");
+  if (!(p->nu > -1.0 && p->nu < 0.5)) return c->fail(FE_EINVAL, "nu out of range");
+  return FE_OK;
+}
+
+int clear_elem_status(fe_ctx *c, hipStream_t st) {
+  c->h_state->elem_status = 0;
+  hipError_t e = hipMemcpyAsync(&c->d_state->elem_status, &c->h_state->elem_status,
+                                sizeof(int32_t), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return c->fail(FE_EDEVICE, "status reset: %s", hipGetErrorString(e));
+  // the pinned source must not change before the copy has run
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return c->fail(FE_EDEVICE, "stream sync: %s", hipGetErrorString(e));
+  return FE_OK;
+}
+
+int install_locked(fe_ctx *c, hipStream_t st) {
+  if (c->ready_tag < 0 || c->ready_tag == c->installed_tag) return FE_OK;
+  const int slot = c->active_slot < 0 ? 0 : 1 - c->active_slot;
+  const size_t pan_bytes = (size_t)c->S.panel_entries * c->tsize;
+  const size_t dinv_bytes = (size_t)c->P.n * c->tsize;
+  HIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_slot_free[slot], 0));
+  HIP_TRY(hipMemcpyAsync(c->d_panels[slot], c->h_stage, pan_bytes, hipMemcpyHostToDevice,
+                         c->copy_stream));
+  HIP_TRY(hipMemcpyAsync(c->d_dinv[slot], (char *)c->h_stage + pan_bytes, dinv_bytes,
+                         hipMemcpyHostToDevice, c->copy_stream));
+  HIP_TRY(hipEventRecord(c->ev_upload_done, c->copy_stream));
+  c->upload_issued = true;
+  HIP_TRY(hipStreamWaitEvent(st, c->ev_upload_done, 0));
+  if (c->active_slot >= 0) HIP_TRY(hipEventRecord(c->ev_slot_free[c->active_slot], st));
+  c->active_slot = slot;
+  c->installed_tag = c->ready_tag;
+  return FE_OK;
+}
+
+int factor_async_impl(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
+  std::unique_lock<std::mutex> lk(c->mu);
+  if (c->job_pending || c->job_running) return c->fail(FE_EBUSY, "factorisation in progress");
+  HIP_TRY(hipEventRecord(c->ev_snap_ready, st));
+  HIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_snap_ready, 0));
+  HIP_TRY(hipMemcpyAsync(c->h_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToHost,
+                         c->copy_stream));
+  HIP_TRY(hipEventRecord(c->ev_snap_done, c->copy_stream));
+  c->job_tag = tag;
+  c->job_pending = true;
+  c->cv.notify_all();
+  return FE_OK;
+}
+
+int factor_wait_impl(fe_ctx *c, int64_t tag) {
+  std::unique_lock<std::mutex> lk(c->mu);
+  c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+  if (c->job_status != FE_OK) return c->fail(c->job_status, "%s", c->job_err.c_str());
+  if (c->ready_tag < tag) return c->fail(FE_ESTATE, "no factorisation job with tag %lld",
+                                         (long long)tag);
+  return FE_OK;
+}
+
+template <typename T>
+int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step_opts *o,
+              double *a_out, hipStream_t st, fe_step_stats *stats) {
+  const int64_t n = c->P.n;
+  const int64_t step = c->step_count;
+  T *A = (T *)c->d_A;
+  int rc = assemble<T>(c, p, q, v, A, c->d_b, st);
+  if (rc) return rc;
+  const int R = o->refresh, d = o->lag;
+  if (R > 0 && step % R == 0) {
+    bool busy;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      busy = c->job_pending || c->job_running;
+    }
+    if (busy && o->mode == FE_FACTOR_DETERMINISTIC) {
+      std::unique_lock<std::mutex> lk(c->mu);
+      c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+      busy = false;
+    }
+    if (!busy) {
+      rc = factor_async_impl(c, A, step, st);
+      if (rc) return rc;
+    }
+  }
+  if (R > 0) {
+    std::unique_lock<std::mutex> lk(c->mu);
+    if (o->mode == FE_FACTOR_DETERMINISTIC) {
+      if (step - d >= 0) {
+        const int64_t req = ((step - d) / R) * R;
+        if (c->installed_tag != req) {
+          lk.unlock();
+          rc = factor_wait_impl(c, req);
+          if (rc) return rc;
+          lk.lock();
+          rc = install_locked(c, st);
+          if (rc) return rc;
+        }
+      }
+    } else {
+      rc = install_locked(c, st);
+      if (rc) return rc;
+    }
+  }
+  double *x = c->d_a;
+  if (!(o->warm_start && c->have_prev_a)) launch_zero(st, n, x);
+  fe_solve_stats ss;
+  rc = pcg<T>(c, A, c->d_b, x, o->rel_tol, o->max_it, st, &ss);
+  c->have_prev_a = true;
+  if (c->h_state->elem_status) {
+    clear_elem_status(c, st);
+    return c->fail(FE_EINVERTED, "inverted element (det F <= 0) at step %lld", (long long)step);
+  }
+  if (rc && rc != FE_ENOTCONV) return rc;
+  launch_integrate(st, n, p->h, x, q, v);
+  if (a_out) {
+    hipError_t e = hipMemcpyAsync(a_out, x, n * 8, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return c->fail(FE_EDEVICE, "a_out copy: %s", hipGetErrorString(e));
+  }
+  if (stats) {
+    stats->solve = ss;
+    stats->step = step;
+    stats->factor_lag = ss.factor_tag >= 0 ? step - ss.factor_tag : -1;
+  }
+  c->step_count = step + 1;
+  return rc;
+}
+
+template <typename T>
+int adjoint_impl(fe_ctx *c, const double *q_n, const double *v_n, const double *v_np1,
+                 const double *lq_in, const double *lv_in, double *lq_out, double *lv_out,
+                 double *dE, const fe_params *p, const fe_step_opts *o, hipStream_t st,
+                 fe_solve_stats *stats) {
+  const int64_t n = c->P.n;
+  T *A = (T *)c->d_A;
+  // A at q_n (b is not needed but assembled alongside)
+  int rc = assemble<T>(c, p, q_n, v_n, A, c->d_b, st);
+  if (rc) return rc;
+  if (o && o->refresh > 0 && c->active_slot < 0) {
+    // no factor yet: factor this A synchronously
+    const int64_t tag = (int64_t(1) << 40) + c->step_count;
+    rc = factor_wait_impl(c, -1);  // let a running job finish first
+    if (rc) return rc;
+    rc = factor_async_impl(c, A, tag, st);
+    if (rc) return rc;
+    rc = factor_wait_impl(c, tag);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    rc = install_locked(c, st);
+    if (rc) return rc;
+  }
+  launch_abar(st, n, p->h, lq_in, lv_in, c->d_dof_fixed, c->d_abar);
+  launch_zero(st, n, c->d_mu);
+  fe_solve_stats ss;
+  rc = pcg<T>(c, A, c->d_abar, c->d_mu, o ? o->rel_tol : 1e-10, o ? o->max_it : 1000, st, &ss);
+  if (c->h_state->elem_status) {
+    clear_elem_status(c, st);
+    return c->fail(FE_EINVERTED, "inverted element in the adjoint step");
+  }
+  if (rc && rc != FE_ENOTCONV) return rc;
+  launch_zero(st, n, c->d_Kmu);
+  launch_zero(st, n, c->d_Mmu);
+  launch_zero(st, n, c->d_Tmv);
+  const ElemParams ep = to_elem(p);
+  launch_adjoint_element<T>(st, c->elem_type, c->P.n_elems, c->d_conn, c->d_X, q_n, c->d_mu,
+                            v_np1, p->E, ep, c->d_Kmu, c->d_Mmu, c->d_Tmv, dE);
+  launch_adjoint_combine(st, n, p->h, p->alpha, p->beta, lq_in, lv_in, c->d_Kmu, c->d_Mmu,
+                         c->d_Tmv, lq_out, lv_out);
+  if (stats) *stats = ss;
+  return rc;
+}
+
+}  // namespace
+
+fe_ctx::~fe_ctx() {
+  if (th.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      quit = true;
+    }
+    cv.notify_all();
+    th.join();
+  }
+  if (bound) {
+    (void)hipSetDevice(device);
+    drain_timing(this);
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (copy_stream) (void)hipStreamSynchronize(copy_stream);
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_Asnap) (void)hipHostFree(h_Asnap);
+    if (h_stage) (void)hipHostFree(h_stage);
+    for (hipEvent_t e : {ev_snap_ready, ev_snap_done, ev_upload_done, ev_slot_free[0],
+                         ev_slot_free[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
+  }
+}
+
+// =================================================================== C ABI
+extern "C" {
+
+int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_build_opts *opts,
+                     fe_ctx **out) {
+  g_build_error.clear();
+  if (!mesh || !out || !mesh->conn || !mesh->X) {
+    g_build_error = "NULL argument";
+    return FE_EINVAL;
+  }
+  if (mesh->elem_type != FE_TET4 && mesh->elem_type != FE_HEX8) {
+    g_build_error = "elem_type must be FE_TET4 or FE_HEX8";
+    return FE_EINVAL;
+  }
+  fe_ctx *c = nullptr;
+  try {
+    c = new fe_ctx();
+    c->elem_type = mesh->elem_type;
+    c->nen = mesh->elem_type;
+    c->n_threads = opts && opts->n_threads > 0 ? opts->n_threads
+                                               : (int)std::max(1u, std::thread::hardware_concurrency());
+    std::string e = build_pattern(mesh->n_nodes, mesh->n_elems, c->nen, mesh->conn, fixed_dof, c->P);
+    if (e.empty()) {
+      // rest volume check (signed, per element)
+      const double *X = mesh->X;
+      for (int64_t el = 0; el < mesh->n_elems && e.empty(); ++el) {
+        const int32_t *cn = mesh->conn + el * c->nen;
+        int a0 = 0, a1 = 1, a2 = c->nen == 8 ? 3 : 2, a3 = c->nen == 8 ? 4 : 3;
+        double d[3][3];
+        for (int i = 0; i < 3; ++i) {
+          d[0][i] = X[3 * cn[a1] + i] - X[3 * cn[a0] + i];
+          d[1][i] = X[3 * cn[a2] + i] - X[3 * cn[a0] + i];
+          d[2][i] = X[3 * cn[a3] + i] - X[3 * cn[a0] + i];
+        }
+        const double det = d[0][0] * (d[1][1] * d[2][2] - d[1][2] * d[2][1]) -
+                           d[0][1] * (d[1][0] * d[2][2] - d[1][2] * d[2][0]) +
+                           d[0][2] * (d[1][0] * d[2][1] - d[1][1] * d[2][0]);
+        if (!(det > 0)) e = "element " + std::to_string(el) + " has non-positive rest volume";
+      }
+    }
+    if (e.empty()) {
+      c->X.assign(mesh->X, mesh->X + 3 * (int64_t)mesh->n_nodes);
+      e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, c->S);
+    }
+    if (!e.empty()) {
+      g_build_error = e;
+      delete c;
+      return FE_EINVAL;
+    }
+    const double avg = (double)c->P.col_idx.size() / (double)std::max<int64_t>(1, c->P.n);
+    c->spmv_lanes = spmv_lanes_for(avg);
+  } catch (const std::bad_alloc &) {
+    g_build_error = "out of host memory";
+    delete c;
+    return FE_ENOMEM;
+  } catch (const std::exception &ex) {
+    g_build_error = ex.what();
+    delete c;
+    return FE_EINVAL;
+  }
+  *out = c;
+  return FE_OK;
+}
+
+int fe_query(fe_ctx *c, int32_t prec, fe_sizes *o) {
+  if (!c || !o) return FE_EINVAL;
+  if (prec != FE_PREC_FP64 && prec != FE_PREC_MIXED) return c->fail(FE_EINVAL, "bad precision");
+  const Layout L = make_layout(c, prec);
+  o->n_dofs = c->P.n;
+  o->nnz = (int64_t)c->P.col_idx.size();
+  o->n_elems = c->P.n_elems;
+  o->map_len = (int64_t)c->P.tmap.size();
+  o->n_supernodes = (int64_t)c->S.sn.size();
+  o->n_levels = c->S.n_levels;
+  o->factor_entries = c->S.panel_entries;
+  o->factor_lower = c->S.lower_entries;
+  o->factor_flops = c->S.flops;
+  o->ws_bytes = L.total;
+  o->compact_map = c->P.compact_ok ? 1 : 0;
+  o->pad_ = 0;
+  return FE_OK;
+}
+
+int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (c->bound) return c->fail(FE_ESTATE, "context already bound");
+  if (prec != FE_PREC_FP64 && prec != FE_PREC_MIXED) return c->fail(FE_EINVAL, "bad precision");
+  const Layout L = make_layout(c, prec);
+  if (!d_ws || ws_bytes < L.total)
+    return c->fail(FE_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)ws_bytes,
+                   (long long)L.total);
+  if (((uintptr_t)d_ws) % 256 != 0) return c->fail(FE_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipGetDevice(&c->device));
+  c->prec = prec;
+  c->tsize = prec == FE_PREC_MIXED ? 4 : 8;
+  c->ws = (char *)d_ws;
+  c->ws_bytes = ws_bytes;
+  char *w = c->ws;
+  c->d_row_ptr = ptr_at<int32_t>(w, L, L_ROWPTR);
+  c->d_col = ptr_at<int32_t>(w, L, L_COL);
+  c->d_conn = ptr_at<int32_t>(w, L, L_CONN);
+  c->d_slot = ptr_at<uint8_t>(w, L, L_SLOT);
+  c->d_smap = ptr_at<int32_t>(w, L, L_SMAP);
+  c->d_fds = ptr_at<int32_t>(w, L, L_FDS);
+  c->d_dof_fixed = ptr_at<uint8_t>(w, L, L_DOFFIX);
+  c->d_X = ptr_at<double>(w, L, L_X);
+  c->d_sn = ptr_at<SnDev>(w, L, L_SN);
+  c->d_rows = ptr_at<int32_t>(w, L, L_ROWS);
+  c->d_ftiles = ptr_at<TileDev>(w, L, L_FT);
+  c->d_btiles = ptr_at<TileDev>(w, L, L_BT);
+  c->d_panels[0] = w + L.off[L_PAN0];
+  c->d_panels[1] = w + L.off[L_PAN1];
+  c->d_dinv[0] = w + L.off[L_DINV0];
+  c->d_dinv[1] = w + L.off[L_DINV1];
+  c->d_jdinv = ptr_at<double>(w, L, L_JDINV);
+  c->d_r = ptr_at<double>(w, L, L_R);
+  c->d_z = ptr_at<double>(w, L, L_Z);
+  c->d_p = ptr_at<double>(w, L, L_P);
+  c->d_q = ptr_at<double>(w, L, L_Q);
+  c->d_tmp = ptr_at<double>(w, L, L_TMP);
+  c->d_b = ptr_at<double>(w, L, L_B);
+  c->d_a = ptr_at<double>(w, L, L_ACC);
+  c->d_abar = ptr_at<double>(w, L, L_ABAR);
+  c->d_mu = ptr_at<double>(w, L, L_MU);
+  c->d_Kmu = ptr_at<double>(w, L, L_KMU);
+  c->d_Mmu = ptr_at<double>(w, L, L_MMU);
+  c->d_Tmv = ptr_at<double>(w, L, L_TMV);
+  c->d_w = w + L.off[L_W];
+  c->d_y = w + L.off[L_Y];
+  c->d_A = w + L.off[L_A];
+  c->d_part1 = ptr_at<double>(w, L, L_PART1);
+  c->d_part2 = ptr_at<double>(w, L, L_PART2);
+  c->d_state = ptr_at<PcgState>(w, L, L_STATE);
+
+  // host-side resources
+  HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
+  memset(c->h_state, 0, sizeof(PcgState));
+  HIP_TRY(hipHostMalloc(&c->h_Asnap, std::max<size_t>(1, c->P.col_idx.size() * c->tsize),
+                        hipHostMallocDefault));
+  HIP_TRY(hipHostMalloc(&c->h_stage,
+                        std::max<size_t>(1, (c->S.panel_entries + c->P.n) * c->tsize),
+                        hipHostMallocDefault));
+  HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_snap_ready, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_snap_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_upload_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_slot_free[0], hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&c->ev_slot_free[1], hipEventDisableTiming));
+  c->bound = true;
+
+  // upload topology (synchronous copies from pageable host memory)
+  const Pattern &P = c->P;
+  const Symbolic &S = c->S;
+  auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  HIP_TRY(up(c->d_row_ptr, P.row_ptr.data(), P.row_ptr.size() * 4));
+  HIP_TRY(up(c->d_col, P.col_idx.data(), P.col_idx.size() * 4));
+  HIP_TRY(up(c->d_conn, P.conn.data(), P.conn.size() * 4));
+  if (P.compact_ok) HIP_TRY(up(c->d_slot, P.slot.data(), P.slot.size()));
+  else HIP_TRY(up(c->d_smap, P.tmap.data(), P.tmap.size() * 4));
+  HIP_TRY(up(c->d_fds, P.fixed_diag_slot.data(), P.fixed_diag_slot.size() * 4));
+  HIP_TRY(up(c->d_dof_fixed, P.fixed.data(), P.fixed.size()));
+  HIP_TRY(up(c->d_X, c->X.data(), c->X.size() * 8));
+  std::vector<SnDev> sn(S.sn.size());
+  for (size_t s = 0; s < S.sn.size(); ++s)
+    sn[s] = SnDev{S.sn[s].nc, S.sn[s].m, S.sn[s].panel_off, S.sn[s].rows_off};
+  HIP_TRY(up(c->d_sn, sn.data(), sn.size() * sizeof(SnDev)));
+  HIP_TRY(up(c->d_rows, S.rows.data(), S.rows.size() * 4));
+  std::vector<TileDev> ft(S.fwd_tiles.size()), bt(S.bwd_tiles.size());
+  for (size_t i = 0; i < ft.size(); ++i)
+    ft[i] = TileDev{S.fwd_tiles[i].s, S.fwd_tiles[i].r0, S.fwd_tiles[i].c0, 0};
+  for (size_t i = 0; i < bt.size(); ++i)
+    bt[i] = TileDev{S.bwd_tiles[i].s, S.bwd_tiles[i].r0, S.bwd_tiles[i].c0, 0};
+  HIP_TRY(up(c->d_ftiles, ft.data(), ft.size() * sizeof(TileDev)));
+  HIP_TRY(up(c->d_btiles, bt.data(), bt.size() * sizeof(TileDev)));
+  HIP_TRY(up(c->d_state, c->h_state, sizeof(PcgState)));
+  HIP_TRY(hipStreamSynchronize(st));
+
+  // algorithmic bytes per sweep level (lower panel entries + indices + vectors)
+  c->fwd_level_bytes.assign(S.n_levels, 0.0);
+  c->bwd_level_bytes.assign(S.n_levels, 0.0);
+  for (const Supernode &s : S.sn) {
+    const double lower = (double)s.m * s.nc - (double)s.nc * (s.nc - 1) / 2.0;
+    const double bytes = lower * c->tsize + s.m * 4.0 + (s.nc + 2.0 * s.m) * c->tsize;
+    c->fwd_level_bytes[s.level] += bytes;
+    c->bwd_level_bytes[S.n_levels - 1 - s.level] += bytes;
+  }
+  // backward levels are launched top-down: index L of the loop is level nl-1-L
+  c->th = std::thread(factor_main, c);
+  return FE_OK;
+}
+
+int fe_export_pattern(fe_ctx *c, int32_t *row_ptr, int32_t *col_idx, int32_t *map) {
+  if (!c) return FE_EINVAL;
+  if (row_ptr) memcpy(row_ptr, c->P.row_ptr.data(), c->P.row_ptr.size() * 4);
+  if (col_idx) memcpy(col_idx, c->P.col_idx.data(), c->P.col_idx.size() * 4);
+  if (map) memcpy(map, c->P.tmap.data(), c->P.tmap.size() * 4);
+  return FE_OK;
+}
+
+int fe_export_ordering(fe_ctx *c, int32_t *perm, int32_t *sn_ptr) {
+  if (!c) return FE_EINVAL;
+  if (perm) memcpy(perm, c->S.perm.data(), c->S.perm.size() * 4);
+  if (sn_ptr) memcpy(sn_ptr, c->S.sn_ptr.data(), c->S.sn_ptr.size() * 4);
+  return FE_OK;
+}
+
+int fe_assemble(fe_ctx *c, const fe_params *params, const double *q, const double *v,
+                void *A_vals, double *b, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (int rc = check_params(c, params)) return rc;
+  if (!q || !v || !A_vals || !b) return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  if (int rc = clear_elem_status(c, st)) return rc;
+  if (c->prec == FE_PREC_MIXED) assemble<float>(c, params, q, v, (float *)A_vals, b, st);
+  else assemble<double>(c, params, q, v, (double *)A_vals, b, st);
+  HIP_TRY(hipGetLastError());
+  if (int rc = read_state(c, st)) return rc;
+  if (c->h_state->elem_status) {
+    clear_elem_status(c, st);
+    return c->fail(FE_EINVERTED, "inverted element (det F <= 0)");
+  }
+  return FE_OK;
+}
+
+int fe_factor_async(fe_ctx *c, const void *A_vals, int64_t tag, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!A_vals) return c->fail(FE_EINVAL, "NULL A");
+  return factor_async_impl(c, A_vals, tag, (hipStream_t)stream);
+}
+
+int fe_factor_status(fe_ctx *c, int64_t *ready_tag) {
+  if (!c) return FE_EINVAL;
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (ready_tag) *ready_tag = c->ready_tag;
+  if (c->job_pending || c->job_running) return FE_EBUSY;
+  if (c->job_status != FE_OK) return c->fail(c->job_status, "%s", c->job_err.c_str());
+  return FE_OK;
+}
+
+int fe_factor_wait(fe_ctx *c, int64_t tag) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  return factor_wait_impl(c, tag);
+}
+
+int fe_factor_install(fe_ctx *c, int64_t *tag, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = install_locked(c, (hipStream_t)stream);
+  if (tag) *tag = c->active_slot >= 0 ? c->installed_tag : -1;
+  return rc;
+}
+
+int fe_pcg_solve(fe_ctx *c, const void *A_vals, const double *b, double *x, double rel_tol,
+                 int32_t max_it, void *stream, fe_solve_stats *stats) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!A_vals || !b || !x) return c->fail(FE_EINVAL, "NULL buffer");
+  if (!(rel_tol > 0) || max_it <= 0) return c->fail(FE_EINVAL, "bad tolerance or max_it");
+  hipStream_t st = (hipStream_t)stream;
+  if (c->prec == FE_PREC_MIXED)
+    return pcg<float>(c, (const float *)A_vals, b, x, rel_tol, max_it, st, stats);
+  return pcg<double>(c, (const double *)A_vals, b, x, rel_tol, max_it, st, stats);
+}
+
+int fe_step(fe_ctx *c, double *q, double *v, const fe_params *params, const fe_step_opts *opts,
+            double *a_out, void *stream, fe_step_stats *stats) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (int rc = check_params(c, params)) return rc;
+  if (!q || !v || !opts) return c->fail(FE_EINVAL, "NULL argument");
+  if (opts->mode == FE_FACTOR_DETERMINISTIC && opts->refresh > 0 && opts->lag >= opts->refresh)
+    return c->fail(FE_EINVAL, "deterministic mode needs lag < refresh");
+  if (!(opts->rel_tol > 0) || opts->max_it <= 0) return c->fail(FE_EINVAL, "bad rel_tol/max_it");
+  hipStream_t st = (hipStream_t)stream;
+  if (c->prec == FE_PREC_MIXED) return step_impl<float>(c, q, v, params, opts, a_out, st, stats);
+  return step_impl<double>(c, q, v, params, opts, a_out, st, stats);
+}
+
+int fe_step_adjoint(fe_ctx *c, const double *q_n, const double *v_n, const double *v_np1,
+                    const double *lam_q_in, const double *lam_v_in, double *lam_q_out,
+                    double *lam_v_out, double *dE_accum, const fe_params *params,
+                    const fe_step_opts *opts, void *stream, fe_solve_stats *stats) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (int rc = check_params(c, params)) return rc;
+  if (!q_n || !v_n || !v_np1 || !lam_q_in || !lam_v_in || !lam_q_out || !lam_v_out || !dE_accum)
+    return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  if (c->prec == FE_PREC_MIXED)
+    return adjoint_impl<float>(c, q_n, v_n, v_np1, lam_q_in, lam_v_in, lam_q_out, lam_v_out,
+                               dE_accum, params, opts, st, stats);
+  return adjoint_impl<double>(c, q_n, v_n, v_np1, lam_q_in, lam_v_in, lam_q_out, lam_v_out,
+                              dE_accum, params, opts, st, stats);
+}
+
+int fe_spmv(fe_ctx *c, const void *A_vals, const double *x, double *y, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!A_vals || !x || !y) return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  if (c->prec == FE_PREC_MIXED)
+    spmv<float>(c, (const float *)A_vals, x, y, nullptr, nullptr, nullptr, st, nullptr);
+  else
+    spmv<double>(c, (const double *)A_vals, x, y, nullptr, nullptr, nullptr, st, nullptr);
+  HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
+int fe_precond_apply(fe_ctx *c, const void *A_vals, const double *r, double *z, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!r || !z) return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  if (c->active_slot < 0) {
+    if (!A_vals) return c->fail(FE_EINVAL, "no factor installed and A is NULL");
+    if (c->prec == FE_PREC_MIXED)
+      launch_diag_inv<float>(st, c->P.n, c->d_row_ptr, c->d_col, (const float *)A_vals, c->d_jdinv);
+    else
+      launch_diag_inv<double>(st, c->P.n, c->d_row_ptr, c->d_col, (const double *)A_vals, c->d_jdinv);
+  }
+  if (c->prec == FE_PREC_MIXED) precond<float>(c, (const float *)A_vals, r, z, st, false);
+  else precond<double>(c, (const double *)A_vals, r, z, st, false);
+  HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
+int fe_host_factor_apply(fe_ctx *c, const double *A_host, const double *r_host, double *z_host,
+                         int32_t n_rhs) {
+  if (!c) return FE_EINVAL;
+  if (!A_host || !r_host || !z_host || n_rhs < 0) return c->fail(FE_EINVAL, "bad argument");
+  std::vector<double> panels, dinv;
+  std::string e = factorize<double>(c->P, c->S, A_host, c->n_threads, panels, dinv);
+  if (!e.empty()) return c->fail(FE_EFACTOR, "%s", e.c_str());
+  const Symbolic &S = c->S;
+  const int64_t n = c->P.n;
+  std::vector<double> w(n), y(n), t;
+  for (int32_t k = 0; k < n_rhs; ++k) {
+    const double *r = r_host + k * n;
+    double *z = z_host + k * n;
+    for (int64_t i = 0; i < n; ++i) {
+      w[i] = r[i];
+      y[i] = 0.0;
+      z[i] = c->P.fixed[i] ? r[i] : 0.0;
+    }
+    for (const Supernode &s : S.sn) {  // post-order = a valid forward order
+      const int32_t *rw = S.rows.data() + s.rows_off;
+      const double *G = panels.data() + s.panel_off;
+      t.assign(s.m, 0.0);
+      for (int32_t j = 0; j < s.nc; ++j) {
+        const double wj = w[rw[j]];
+        for (int32_t i = j; i < s.m; ++i) t[i] += G[(int64_t)j * s.m + i] * wj;
+      }
+      for (int32_t i = 0; i < s.nc; ++i) y[rw[i]] = t[i];
+      for (int32_t i = s.nc; i < s.m; ++i) w[rw[i]] -= t[i];
+    }
+    for (int64_t si = (int64_t)S.sn.size() - 1; si >= 0; --si) {
+      const Supernode &s = S.sn[si];
+      const int32_t *rw = S.rows.data() + s.rows_off;
+      const double *G = panels.data() + s.panel_off;
+      for (int32_t j = 0; j < s.nc; ++j) {
+        double acc = 0.0;
+        for (int32_t i = j; i < s.m; ++i) {
+          const double vi = i < s.nc ? dinv[rw[i]] * y[rw[i]] : -z[rw[i]];
+          acc += G[(int64_t)j * s.m + i] * vi;
+        }
+        z[rw[j]] = acc;
+      }
+    }
+  }
+  return FE_OK;
+}
+
+int fe_set_kernel_timing(fe_ctx *c, int32_t enable) {
+  if (!c) return FE_EINVAL;
+  c->timing = enable != 0;
+  return FE_OK;
+}
+
+int fe_kernel_times(fe_ctx *c, double *out_ms, int64_t *out_count, double *out_bytes, int32_t n) {
+  if (!c) return FE_EINVAL;
+  drain_timing(c);
+  for (int k = 0; k < 4 && k < n; ++k) {
+    if (out_ms) out_ms[k] = c->t_ms[k];
+    if (out_count) out_count[k] = c->t_count[k];
+    if (out_bytes) out_bytes[k] = c->t_bytes[k];
+    c->t_ms[k] = 0;
+    c->t_count[k] = 0;
+    c->t_bytes[k] = 0;
+  }
+  return FE_OK;
+}
+
+int fe_reset(fe_ctx *c) {
+  if (!c) return FE_EINVAL;
+  std::unique_lock<std::mutex> lk(c->mu);
+  c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+  c->step_count = 0;
+  c->active_slot = -1;
+  c->installed_tag = -1;
+  c->ready_tag = -1;
+  c->job_status = FE_OK;
+  c->have_prev_a = false;
+  return FE_OK;
+}
+
+int fe_destroy(fe_ctx *c) {
+  delete c;
+  return FE_OK;
+}
+
+const char *fe_last_error(fe_ctx *c) {
+  if (!c) return g_build_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Host-side data structures of the FE step library: CSR pattern + element
+// map, nested-dissection ordering, supernodal symbolic structure, and the
+// FP64 numeric LDL^T factor in the explicit-inverse panel form used by the
+// GPU triangular solves.  Pure C++ (no HIP); compiled with the host compiler.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace fe {
+
+// ---------------------------------------------------------------- pattern
+struct Pattern {
+  int32_t n_nodes = 0, n_elems = 0, nen = 0;
+  int64_t n = 0;                          // DOFs
+  std::vector<int32_t> conn;              // [E * nen] element-major copy
+  std::vector<int32_t> row_ptr, col_idx;  // CSR of A (structural, sorted)
+  std::vector<int32_t> tmap;              // canonical map [E * (3 nen)^2]
+  std::vector<int32_t> fixed_diag_slot;   // CSR slot of (d, d) per fixed DOF
+  std::vector<int32_t> fixed_dofs;
+  std::vector<uint8_t> fixed;             // [n]
+  // compact map: slot[e * nen*nen + a*nen + b] = rank of node conn[e][b]
+  // among the free neighbour nodes of conn[e][a] (0xFF: dropped).  Valid when
+  // every node is fully free or fully fixed.
+  bool compact_ok = false;
+  std::vector<uint8_t> slot;
+  std::vector<uint8_t> node_fixed;        // [n_nodes], 1 = all DOFs fixed
+};
+
+// Two counting-sort transposes + merge (paper Sec. 4.2, Sec. 6.1).
+// Returns an error message or "" on success.
+std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
+                          const int32_t *conn, const uint8_t *fixed_dof, Pattern &P);
+
+// ------------------------------------------------- ordering and symbolic
+struct Supernode {
+  int32_t nc = 0;        // own columns (DOFs eliminated in this block)
+  int32_t m = 0;         // rows of the panel: own columns first, then struct
+  int64_t panel_off = 0; // offset (entries) of the m x nc column-major panel
+  int64_t rows_off = 0;  // offset into Symbolic::rows
+  int32_t parent = -1;   // enclosing supernode, -1 for a root
+  int32_t level = 0;     // height above the leaves (dependency level)
+  int32_t first = 0;     // position of the first own column in perm
+};
+
+// Tile of the GPU triangular solves: supernode s, row block r0, column
+// block c0 (tile extents fixed by the kernels' tile sizes).
+struct Tile {
+  int32_t s, r0, c0, pad;
+};
+
+struct Symbolic {
+  int64_t n = 0;                       // DOFs (incl. fixed)
+  int64_t n_free = 0;
+  std::vector<int32_t> perm;           // perm[k] = DOF eliminated k-th
+  std::vector<int32_t> iperm;          // iperm[dof] (fixed DOFs >= n_free)
+  std::vector<int32_t> sn_ptr;         // supernode s owns perm[sn_ptr[s]..)
+  std::vector<Supernode> sn;           // in elimination (post)order
+  std::vector<int32_t> rows;           // panel row DOFs per supernode
+  std::vector<std::vector<int32_t>> children;
+  int32_t n_levels = 0;
+  int64_t panel_entries = 0, lower_entries = 0;
+  double flops = 0.0;
+  // GPU schedules, grouped by level (forward: ascending, backward: descending)
+  std::vector<Tile> fwd_tiles, bwd_tiles;
+  std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
+};
+
+// Tile extents shared with the device kernels.
+constexpr int kFwdRows = 256;   // rows per forward tile (one per thread)
+constexpr int kFwdCols = 128;   // columns per forward tile
+constexpr int kBwdCols = 16;    // columns per backward tile
+constexpr int kBwdRows = 1024;  // rows per backward tile
+
+// Geometric nested dissection on the node graph, supernodes = ND blocks,
+// relaxed (dense) supernodal structure from the assembly tree.
+std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, Symbolic &S);
+
+// ------------------------------------------------------- numeric factor
+// Parallel-for helper (dynamic scheduling on std::threads).
+void parallel_for(int64_t n, int n_threads, const std::function<void(int64_t, int)> &fn);
+
+// FP64 numeric factorisation of A (CSR values in the pattern's order,
+// float or double) with the symbolic structure S.  Output per supernode:
+// G_s = [L11^{-1}; L21 L11^{-1}] (m x nc, column-major) at panel_off in
+// `panels`, and dinv[dof] = 1 / D for every free DOF (1 for fixed DOFs).
+// Returns "" or an error message (non-positive pivot).
+template <typename TA>
+std::string factorize(const Pattern &P, const Symbolic &S, const TA *A, int n_threads,
+                      std::vector<double> &panels, std::vector<double> &dinv);
+
+}  // namespace fe

@@ -1,0 +1,421 @@
+// Solve kernels: CSR SpMV, the CG vector operations and control scalars, the
+// Jacobi fallback, the level-scheduled triangular sweeps of the LDL^T
+// preconditioner, and the backward-Euler update (paper Sec. 5 and Fig.
+// "DataTransfer": the whole preconditioned CG runs on the GPU and only a
+// small status word is read back).
+//
+// Determinism: dot products are reduced per block into a partial array and
+// summed by a one-block control kernel in a fixed order.  The triangular
+// sweeps accumulate with atomics (as the paper's column-major lower solve
+// does), so the preconditioner output is correct to rounding but its
+// summation order is not fixed.
+#include "device.hpp"
+
+namespace fe {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// block-wide sum; result valid in thread 0
+__device__ inline double block_sum(double v) {
+  __shared__ double s_part[kBlock / 64];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) s_part[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += s_part[i];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------- SpMV
+// G lanes per row, FP64 products and row sums of T-valued entries.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const T *__restrict__ val,
+                                                 const double *__restrict__ x, double *__restrict__ y,
+                                                 const double *__restrict__ w, double *part,
+                                                 const PcgState *state) {
+  if (state && state->done) return;
+  const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int sub = threadIdx.x & (G - 1);
+  double sum = 0.0;
+  if (row < n) {
+    const int32_t k0 = row_ptr[row], k1 = row_ptr[row + 1];
+    for (int32_t k = k0 + sub; k < k1; k += G) sum += (double)val[k] * x[col[k]];
+  }
+  for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
+  double d = 0.0;
+  if (row < n && sub == 0) {
+    y[row] = sum;
+    if (w) d = w[row] * sum;
+  }
+  if (part) {
+    d = block_sum(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
+  }
+}
+
+// ---------------------------------------------------------------- CG ops
+__global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *b, const double *Ax,
+                                                     double *r, double *part_rr, double *part_bb) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double rr = 0.0, bb = 0.0;
+  if (i < n) {
+    const double ri = b[i] - Ax[i];
+    r[i] = ri;
+    rr = ri * ri;
+    bb = b[i] * b[i];
+  }
+  rr = block_sum(rr);
+  bb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    part_rr[blockIdx.x] = rr;
+    if (part_bb) part_bb[blockIdx.x] = bb;
+  }
+}
+
+__device__ inline double sum_parts(const double *p, int np) {
+  // one block: fixed-order strided sums then a fixed tree
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += kBlock) v += p[i];
+  return block_sum(v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctl_init(PcgState *s, const double *prr,
+                                                     const double *pbb, int np, double rel_tol) {
+  const double rr = sum_parts(prr, np);
+  const double bb = sum_parts(pbb, np);
+  if (threadIdx.x == 0) {
+    s->rr = rr;
+    s->bb = bb;
+    s->tol2 = rel_tol * rel_tol * bb;
+    s->it = 0;
+    s->status = 0;
+    s->done = (bb == 0.0 || rr <= s->tol2) ? 1 : 0;
+    s->rr_true = rr;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *a, const double *b,
+                                                double *part, const PcgState *state) {
+  if (state && state->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double v = i < n ? a[i] * b[i] : 0.0;
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// rz <- r.z; beta = rz_new / rz_old (first: no beta)
+__global__ __launch_bounds__(kBlock) void k_ctl_rz(PcgState *s, const double *part, int np,
+                                                   int first) {
+  if (s->done) return;
+  const double rz = sum_parts(part, np);
+  if (threadIdx.x == 0) {
+    s->beta = first ? 0.0 : rz / s->rz;
+    s->rz = rz;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctl_alpha(PcgState *s, const double *part, int np) {
+  if (s->done) return;
+  const double pAp = sum_parts(part, np);
+  if (threadIdx.x == 0) {
+    s->pAp = pAp;
+    if (!(pAp > 0.0)) {
+      s->status = 4;
+      s->done = 1;
+      s->alpha = 0.0;
+    } else {
+      s->alpha = s->rz / pAp;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *x, double *r,
+                                                      const double *p, const double *q,
+                                                      double *part, const PcgState *s) {
+  if (s->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const double al = s->alpha;
+  double rr = 0.0;
+  if (i < n) {
+    x[i] += al * p[i];
+    const double ri = r[i] - al * q[i];
+    r[i] = ri;
+    rr = ri * ri;
+  }
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctl_rr(PcgState *s, const double *part, int np) {
+  if (s->done) return;
+  const double rr = sum_parts(part, np);
+  if (threadIdx.x == 0) {
+    s->rr = rr;
+    s->it += 1;
+    if (rr <= s->tol2) s->done = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_ctl_true(PcgState *s, const double *part, int np) {
+  const double rr = sum_parts(part, np);
+  if (threadIdx.x == 0) {
+    s->rr_true = rr;
+    s->rr = rr;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, double *p, const double *z,
+                                                     const PcgState *s, int first) {
+  if (s->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = first ? z[i] : z[i] + s->beta * p[i];
+}
+
+__global__ void k_zero(int64_t n, double *x) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+__global__ void k_integrate(int64_t n, double h, const double *a, double *q, double *v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    const double vn = v[i] + h * a[i];
+    v[i] = vn;
+    q[i] += h * vn;
+  }
+}
+
+// ---------------------------------------------------------------- Jacobi
+template <typename T>
+__global__ void k_diag_inv(int64_t n, const int32_t *row_ptr, const int32_t *col, const T *val,
+                           double *dinv) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+    if (col[k] == i) d += (double)val[k];
+  dinv[i] = d != 0.0 ? 1.0 / d : 1.0;
+}
+
+__global__ void k_jacobi(int64_t n, const double *dinv, const double *r, double *z,
+                         const PcgState *s) {
+  if (s && s->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) z[i] = dinv[i] * r[i];
+}
+
+// ------------------------------------------------------ triangular sweeps
+// prep: w = r (free DOFs), y = 0, z = 0 (free) / r (fixed: identity rows)
+template <typename T>
+__global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
+                           const uint8_t *fixed, const PcgState *s) {
+  if (s && s->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double ri = r[i];
+  w[i] = (T)ri;
+  y[i] = T(0);
+  z[i] = fixed[i] ? ri : 0.0;
+}
+
+constexpr int kFR = 256, kFC = 128;   // forward tile: rows x columns
+constexpr int kBC = 16, kBR = 1024;   // backward tile: columns x rows
+
+// Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
+// rows; own rows (i < nc) accumulate into y, struct rows subtract from w.
+template <typename T>
+__global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
+                                                 const SnDev *__restrict__ sn,
+                                                 const int32_t *__restrict__ rows,
+                                                 const T *__restrict__ panels, T *w, T *y,
+                                                 const PcgState *s) {
+  if (s && s->done) return;
+  __shared__ T s_in[kFC];
+  const TileDev t = tiles[blockIdx.x];
+  const SnDev d = sn[t.s];
+  const int32_t *rw = rows + d.rows_off;
+  const int c0 = t.c0, c1 = min(d.nc, c0 + kFC);
+  if ((int)threadIdx.x < c1 - c0) s_in[threadIdx.x] = w[rw[c0 + threadIdx.x]];
+  __syncthreads();
+  const int i = t.r0 + (int)threadIdx.x;
+  if (i >= d.m) return;
+  const int jend = (i < d.nc) ? min(c1, i + 1) : c1;
+  if (jend <= c0) return;
+  const T *G = panels + d.panel_off + (int64_t)c0 * d.m + i;
+  T acc = T(0);
+  int j = c0;
+  for (; j + 4 <= jend; j += 4) {
+    acc += G[0] * s_in[j - c0];
+    acc += G[(int64_t)d.m] * s_in[j + 1 - c0];
+    acc += G[2 * (int64_t)d.m] * s_in[j + 2 - c0];
+    acc += G[3 * (int64_t)d.m] * s_in[j + 3 - c0];
+    G += 4 * (int64_t)d.m;
+  }
+  for (; j < jend; ++j) {
+    acc += G[0] * s_in[j - c0];
+    G += d.m;
+  }
+  if (i < d.nc) atomicAdd(y + rw[i], acc);
+  else atomicAdd(w + rw[i], -acc);
+}
+
+// Backward tile: x[rows[j]] += sum_{i in tile rows} G[i, j] v_i with
+// v_i = dinv y (own rows) or -x[rows[i]] (struct rows, already final).
+template <typename T>
+__global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
+                                                 const SnDev *__restrict__ sn,
+                                                 const int32_t *__restrict__ rows,
+                                                 const T *__restrict__ panels,
+                                                 const T *__restrict__ dinv,
+                                                 const T *__restrict__ y, double *z,
+                                                 const PcgState *s) {
+  if (s && s->done) return;
+  __shared__ T s_v[kBR];
+  const TileDev t = tiles[blockIdx.x];
+  const SnDev d = sn[t.s];
+  const int32_t *rw = rows + d.rows_off;
+  const int r0 = t.r0, r1 = min(d.m, r0 + kBR);
+  for (int k = threadIdx.x; k < r1 - r0; k += 256) {
+    const int i = r0 + k;
+    const int32_t dof = rw[i];
+    s_v[k] = (i < d.nc) ? dinv[dof] * y[dof] : (T)(-z[dof]);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int cc = 0; cc < kBC / 4; ++cc) {
+    const int j = t.c0 + wv * (kBC / 4) + cc;
+    if (j >= d.nc) break;
+    const int ibeg = max(r0, j);
+    const T *G = panels + d.panel_off + (int64_t)j * d.m;
+    double acc = 0.0;
+    T part = T(0);
+    for (int i = ibeg + lane; i < r1; i += 64) part += G[i] * s_v[i - r0];
+    acc = wave_sum((double)part);
+    if (lane == 0 && ibeg < r1) atomicAdd(z + rw[j], acc);
+  }
+}
+
+}  // namespace
+
+int spmv_lanes_for(double avg) {
+  if (avg > 48) return 16;
+  if (avg > 24) return 8;
+  if (avg > 12) return 4;
+  return 2;
+}
+
+template <typename T>
+void launch_spmv(hipStream_t st, int64_t n, int G, const int32_t *row_ptr, const int32_t *col,
+                 const T *val, const double *x, double *y, const double *w, double *part,
+                 int *n_part, const PcgState *state) {
+  const int64_t rows_per_block = kBlock / G;
+  const unsigned blocks = (unsigned)((n + rows_per_block - 1) / rows_per_block);
+  if (n_part) *n_part = (int)blocks;
+  switch (G) {
+    case 16: k_spmv<T, 16><<<blocks, kBlock, 0, st>>>(n, row_ptr, col, val, x, y, w, part, state); break;
+    case 8: k_spmv<T, 8><<<blocks, kBlock, 0, st>>>(n, row_ptr, col, val, x, y, w, part, state); break;
+    case 4: k_spmv<T, 4><<<blocks, kBlock, 0, st>>>(n, row_ptr, col, val, x, y, w, part, state); break;
+    default: k_spmv<T, 2><<<blocks, kBlock, 0, st>>>(n, row_ptr, col, val, x, y, w, part, state); break;
+  }
+}
+
+int cg_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+void launch_residual(hipStream_t st, int64_t n, const double *b, const double *Ax, double *r,
+                     double *prr, double *pbb) {
+  k_residual<<<cg_blocks(n), kBlock, 0, st>>>(n, b, Ax, r, prr, pbb);
+}
+void launch_ctl_init(hipStream_t st, PcgState *s, const double *prr, const double *pbb, int np,
+                     double rel_tol) {
+  k_ctl_init<<<1, kBlock, 0, st>>>(s, prr, pbb, np, rel_tol);
+}
+void launch_dot(hipStream_t st, int64_t n, const double *a, const double *b, double *part,
+                const PcgState *state) {
+  k_dot<<<cg_blocks(n), kBlock, 0, st>>>(n, a, b, part, state);
+}
+void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int first) {
+  k_ctl_rz<<<1, kBlock, 0, st>>>(s, part, np, first);
+}
+void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np) {
+  k_ctl_alpha<<<1, kBlock, 0, st>>>(s, part, np);
+}
+void launch_update_xr(hipStream_t st, int64_t n, double *x, double *r, const double *p,
+                      const double *q, double *part, const PcgState *state) {
+  k_update_xr<<<cg_blocks(n), kBlock, 0, st>>>(n, x, r, p, q, part, state);
+}
+void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np) {
+  k_ctl_rr<<<1, kBlock, 0, st>>>(s, part, np);
+}
+void launch_ctl_true(hipStream_t st, PcgState *s, const double *part, int np) {
+  k_ctl_true<<<1, kBlock, 0, st>>>(s, part, np);
+}
+void launch_update_p(hipStream_t st, int64_t n, double *p, const double *z, const PcgState *state,
+                     int first) {
+  k_update_p<<<cg_blocks(n), kBlock, 0, st>>>(n, p, z, state, first);
+}
+void launch_zero(hipStream_t st, int64_t n, double *x) {
+  if (n > 0) k_zero<<<cg_blocks(n), kBlock, 0, st>>>(n, x);
+}
+void launch_integrate(hipStream_t st, int64_t n, double h, const double *a, double *q,
+                      double *v) {
+  k_integrate<<<cg_blocks(n), kBlock, 0, st>>>(n, h, a, q, v);
+}
+
+template <typename T>
+void launch_diag_inv(hipStream_t st, int64_t n, const int32_t *row_ptr, const int32_t *col,
+                     const T *val, double *dinv) {
+  k_diag_inv<T><<<cg_blocks(n), kBlock, 0, st>>>(n, row_ptr, col, val, dinv);
+}
+void launch_jacobi(hipStream_t st, int64_t n, const double *dinv, const double *r, double *z,
+                   const PcgState *state) {
+  k_jacobi<<<cg_blocks(n), kBlock, 0, st>>>(n, dinv, r, z, state);
+}
+
+template <typename T>
+void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, double *z,
+                     const uint8_t *fixed, const PcgState *state) {
+  k_tri_prep<T><<<cg_blocks(n), kBlock, 0, st>>>(n, r, w, y, z, fixed, state);
+}
+template <typename T>
+void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state) {
+  if (n_tiles > 0) k_tri_fwd<T><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state);
+}
+template <typename T>
+void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+                    const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
+                    const PcgState *state) {
+  if (n_tiles > 0)
+    k_tri_bwd<T><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+}
+
+#define FE_INST(T)                                                                             \
+  template void launch_spmv<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *,    \
+                               const T *, const double *, double *, const double *, double *,  \
+                               int *, const PcgState *);                                       \
+  template void launch_diag_inv<T>(hipStream_t, int64_t, const int32_t *, const int32_t *,     \
+                                   const T *, double *);                                       \
+  template void launch_tri_prep<T>(hipStream_t, int64_t, const double *, T *, T *, double *,   \
+                                   const uint8_t *, const PcgState *);                         \
+  template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
+                                  const int32_t *, const T *, T *, T *, const PcgState *);     \
+  template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
+                                  const int32_t *, const T *, const T *, const T *, double *,  \
+                                  const PcgState *);
+FE_INST(float)
+FE_INST(double)
+#undef FE_INST
+
+}  // namespace fe

@@ -1,0 +1,376 @@
+"""Python front end of the FE step library: torch owns device memory and the
+stream; every computation happens in the HIP library behind the C ABI.
+
+``FEContext`` mirrors the C entry points one to one.  ``Simulation`` bundles a
+context with the state and parameters of one mesh.  ``RolloutFn`` is the
+``torch.autograd.Function`` of a k-step rollout: forward keeps a checkpoint of
+(q, v) every ``checkpoint_every`` steps, backward recomputes each segment and
+runs the adjoint step (``fe_step_adjoint``) in reverse, returning gradients
+with respect to the per-element Young's moduli and the initial state.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class StepOptions:
+    rel_tol: float = 1e-8
+    max_it: int = 500
+    refresh: int = 1
+    lag: int = 0
+    mode: int = L.FE_FACTOR_DETERMINISTIC
+    warm_start: int = 0
+
+    def c(self):
+        return L.fe_step_opts(self.rel_tol, self.max_it, self.refresh, self.lag, self.mode,
+                              self.warm_start, 0)
+
+
+class Params:
+    """Physical parameters; E and f_nodal are kept as device tensors."""
+
+    def __init__(self, h, alpha, beta, rho, nu, material, gravity, E, f_nodal=None,
+                 device="cuda"):
+        self.h, self.alpha, self.beta, self.rho, self.nu = h, alpha, beta, rho, nu
+        self.material = int(material)
+        self.gravity = [float(g) for g in gravity]
+        self.E = torch.as_tensor(np.asarray(E), dtype=torch.float64, device=device).contiguous() \
+            if not isinstance(E, torch.Tensor) else E.to(device=device, dtype=torch.float64).contiguous()
+        self.f_nodal = None
+        if f_nodal is not None:
+            f = f_nodal if isinstance(f_nodal, torch.Tensor) else torch.as_tensor(np.asarray(f_nodal))
+            self.f_nodal = f.to(device=device, dtype=torch.float64).reshape(-1).contiguous()
+
+    def c(self):
+        p = L.fe_params()
+        p.h, p.alpha, p.beta, p.rho, p.nu = self.h, self.alpha, self.beta, self.rho, self.nu
+        p.material = self.material
+        p.pad_ = 0
+        for i in range(3):
+            p.gravity[i] = self.gravity[i]
+        p.E = self.E.data_ptr()
+        p.f_nodal = self.f_nodal.data_ptr() if self.f_nodal is not None else None
+        return p
+
+    def with_E(self, E):
+        q = Params.__new__(Params)
+        q.__dict__.update(self.__dict__)
+        q.E = E.to(dtype=torch.float64).contiguous()
+        return q
+
+
+class FEContext:
+    """One library context bound to a caller-owned torch workspace."""
+
+    def __init__(self, X, conn, elem_type, fixed=None, prec=L.FE_PREC_FP64, leaf_nodes=0,
+                 n_threads=0, device="cuda"):
+        self.lib = L.load()
+        X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1)
+        conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1)
+        self.n_nodes = X.size // 3
+        self.nen = int(elem_type)
+        self.n_elems = conn.size // self.nen
+        mesh = L.fe_mesh(self.n_nodes, self.n_elems, int(elem_type),
+                         conn.ctypes.data_as(C.c_void_p), X.ctypes.data_as(C.c_void_p))
+        fx = None
+        if fixed is not None:
+            fixed = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(-1)
+            fx = fixed.ctypes.data_as(C.c_void_p)
+        opts = L.fe_build_opts(int(leaf_nodes), int(n_threads))
+        h = C.c_void_p()
+        L.check(self.lib.fe_build_pattern(C.byref(mesh), fx, C.byref(opts), C.byref(h)), None)
+        self.h = h
+        self.prec = int(prec)
+        self.device = torch.device(device)
+        self.sizes = self.query(self.prec)
+        self.ws = None
+        self.bound = False
+
+    # ---- lifetime -------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value is not None:
+            if self.bound:
+                torch.cuda.synchronize(self.device)
+            self.lib.fe_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        return L.check(rc, self.h)
+
+    def _vec(self, t, name, n=None):
+        """Validate a device FP64 vector argument before it reaches a kernel."""
+        n = self.sizes.n_dofs if n is None else n
+        if t is None:
+            raise ValueError(f"{name} is None")
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be a contiguous float64 tensor of {n} entries")
+        return t
+
+    def _vals(self, A):
+        if not isinstance(A, torch.Tensor) or A.device.type != "cuda":
+            raise ValueError("A must be a CUDA tensor")
+        if A.dtype != self.value_dtype or not A.is_contiguous() or A.numel() != self.sizes.nnz:
+            raise ValueError(f"A must be a contiguous {self.value_dtype} tensor of "
+                             f"{self.sizes.nnz} entries")
+        return A
+
+    def _params(self, p):
+        self._vec(p.E, "params.E", self.n_elems)
+        if p.f_nodal is not None:
+            self._vec(p.f_nodal, "params.f_nodal")
+        return p
+
+    # ---- host-only entry points ----------------------------------------
+    def query(self, prec):
+        s = L.fe_sizes()
+        self._chk(self.lib.fe_query(self.h, int(prec), C.byref(s)))
+        return s
+
+    def export_pattern(self):
+        s = self.sizes
+        rp = np.empty(s.n_dofs + 1, dtype=np.int32)
+        ci = np.empty(s.nnz, dtype=np.int32)
+        mp = np.empty(s.map_len, dtype=np.int32)
+        self._chk(self.lib.fe_export_pattern(self.h, rp.ctypes.data_as(C.c_void_p),
+                                             ci.ctypes.data_as(C.c_void_p),
+                                             mp.ctypes.data_as(C.c_void_p)))
+        return rp, ci, mp
+
+    def export_ordering(self):
+        s = self.sizes
+        perm = np.empty(s.n_dofs, dtype=np.int32)
+        snp = np.empty(s.n_supernodes + 1, dtype=np.int32)
+        self._chk(self.lib.fe_export_ordering(self.h, perm.ctypes.data_as(C.c_void_p),
+                                              snp.ctypes.data_as(C.c_void_p)))
+        return perm, snp
+
+    def host_factor_apply(self, A_host, r_host):
+        """Host-only: factor FP64 CSR values and apply P^{-1} to rows of r."""
+        A = np.ascontiguousarray(A_host, dtype=np.float64)
+        r = np.ascontiguousarray(np.atleast_2d(r_host), dtype=np.float64)
+        z = np.empty_like(r)
+        self._chk(self.lib.fe_host_factor_apply(self.h, A.ctypes.data_as(C.c_void_p),
+                                                r.ctypes.data_as(C.c_void_p),
+                                                z.ctypes.data_as(C.c_void_p), r.shape[0]))
+        return z
+
+    # ---- device entry points -------------------------------------------
+    @property
+    def value_dtype(self):
+        return torch.float32 if self.prec == L.FE_PREC_MIXED else torch.float64
+
+    def bind(self):
+        if self.bound:
+            return
+        nbytes = int(self.sizes.ws_bytes)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_ptr = self.ws.data_ptr() + off
+        self._chk(self.lib.fe_bind(self.h, self.prec, C.c_void_p(self._ws_ptr), nbytes, _stream()))
+        self.bound = True
+
+    def new_values(self):
+        return torch.zeros(self.sizes.nnz, dtype=self.value_dtype, device=self.device)
+
+    def new_vector(self):
+        return torch.zeros(self.sizes.n_dofs, dtype=torch.float64, device=self.device)
+
+    def assemble(self, params: Params, q, v, A=None, b=None):
+        self.bind()
+        A = self._vals(self.new_values() if A is None else A)
+        b = self._vec(self.new_vector() if b is None else b, "b")
+        self._vec(q, "q"), self._vec(v, "v"), self._params(params)
+        pc = params.c()
+        self._chk(self.lib.fe_assemble(self.h, C.byref(pc), _ptr(q), _ptr(v), _ptr(A), _ptr(b),
+                                       _stream()))
+        return A, b
+
+    def factor_async(self, A, tag):
+        self.bind()
+        self._vals(A)
+        self._chk(self.lib.fe_factor_async(self.h, _ptr(A), int(tag), _stream()))
+
+    def factor_wait(self, tag):
+        self._chk(self.lib.fe_factor_wait(self.h, int(tag)))
+
+    def factor_status(self):
+        t = C.c_int64()
+        rc = self.lib.fe_factor_status(self.h, C.byref(t))
+        return rc, t.value
+
+    def factor_install(self):
+        t = C.c_int64()
+        self._chk(self.lib.fe_factor_install(self.h, C.byref(t), _stream()))
+        return t.value
+
+    def factorize_now(self, A, tag=0):
+        """Synchronous convenience: factor A and install it."""
+        self.factor_async(A, tag)
+        self.factor_wait(tag)
+        return self.factor_install()
+
+    def pcg_solve(self, A, b, x=None, rel_tol=1e-8, max_it=1000, check=True):
+        self.bind()
+        x = self._vec(self.new_vector() if x is None else x, "x")
+        self._vals(A), self._vec(b, "b")
+        st = L.fe_solve_stats()
+        rc = self.lib.fe_pcg_solve(self.h, _ptr(A), _ptr(b), _ptr(x), float(rel_tol),
+                                   int(max_it), _stream(), C.byref(st))
+        if check and rc != L.FE_ENOTCONV:
+            self._chk(rc)
+        return x, st
+
+    def step(self, q, v, params: Params, opts: StepOptions, a_out=None):
+        self.bind()
+        self._vec(q, "q"), self._vec(v, "v"), self._params(params)
+        if a_out is not None:
+            self._vec(a_out, "a_out")
+        pc = params.c()
+        oc = opts.c()
+        st = L.fe_step_stats()
+        self._chk(self.lib.fe_step(self.h, _ptr(q), _ptr(v), C.byref(pc), C.byref(oc),
+                                   _ptr(a_out), _stream(), C.byref(st)))
+        return st
+
+    def step_adjoint(self, q_n, v_n, v_np1, lq_in, lv_in, lq_out, lv_out, dE, params: Params,
+                     opts: StepOptions):
+        self.bind()
+        for t, nm in ((q_n, "q_n"), (v_n, "v_n"), (v_np1, "v_np1"), (lq_in, "lam_q_in"),
+                      (lv_in, "lam_v_in"), (lq_out, "lam_q_out"), (lv_out, "lam_v_out")):
+            self._vec(t, nm)
+        self._vec(dE, "dE", self.n_elems), self._params(params)
+        pc = params.c()
+        oc = opts.c()
+        st = L.fe_solve_stats()
+        self._chk(self.lib.fe_step_adjoint(self.h, _ptr(q_n), _ptr(v_n), _ptr(v_np1),
+                                           _ptr(lq_in), _ptr(lv_in), _ptr(lq_out), _ptr(lv_out),
+                                           _ptr(dE), C.byref(pc), C.byref(oc), _stream(),
+                                           C.byref(st)))
+        return st
+
+    def spmv(self, A, x, y=None):
+        self.bind()
+        y = self._vec(self.new_vector() if y is None else y, "y")
+        self._vals(A), self._vec(x, "x")
+        self._chk(self.lib.fe_spmv(self.h, _ptr(A), _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def precond_apply(self, r, A=None, z=None):
+        self.bind()
+        z = self._vec(self.new_vector() if z is None else z, "z")
+        self._vec(r, "r")
+        if A is not None:
+            self._vals(A)
+        self._chk(self.lib.fe_precond_apply(self.h, _ptr(A), _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def set_kernel_timing(self, on=True):
+        self._chk(self.lib.fe_set_kernel_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        ms = (C.c_double * 4)()
+        cnt = (C.c_int64 * 4)()
+        by = (C.c_double * 4)()
+        self._chk(self.lib.fe_kernel_times(self.h, ms, cnt, by, 4))
+        names = ["spmv", "trisolve_fwd", "trisolve_bwd", "element"]
+        return {n: {"ms": ms[i], "count": cnt[i], "bytes": by[i]} for i, n in enumerate(names)}
+
+    def reset(self):
+        self._chk(self.lib.fe_reset(self.h))
+
+
+class Simulation:
+    """A mesh + parameters + state driven through one FEContext.
+
+    ``workload`` is any object with the attributes of ``synth.Workload``.
+    """
+
+    def __init__(self, workload, prec=L.FE_PREC_FP64, device="cuda", leaf_nodes=0, n_threads=0):
+        w = workload
+        self.w = w
+        self.ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec, leaf_nodes, n_threads, device)
+        self.params = Params(w.h, w.alpha, w.beta, w.rho, w.nu, w.material, w.gravity, w.E,
+                             w.f_nodal, device)
+        self.device = device
+        self.q = torch.as_tensor(w.X.reshape(-1).copy(), device=device)
+        self.v = torch.zeros_like(self.q)
+
+    def opts(self, **kw):
+        base = dict(rel_tol=self.w.rel_tol, max_it=2000, refresh=self.w.refresh, lag=self.w.lag)
+        base.update(kw)
+        return StepOptions(**base)
+
+    def step(self, opts=None, a_out=None):
+        return self.ctx.step(self.q, self.v, self.params, opts or self.opts(), a_out)
+
+
+class RolloutFn(torch.autograd.Function):
+    """q_T = rollout(E, q0, v0) with adjoint gradients (checkpointed)."""
+
+    @staticmethod
+    def forward(fctx, E, q0, v0, ctx: FEContext, params: Params, nsteps: int,
+                checkpoint_every: int, opts: StepOptions):
+        p = params.with_E(E.detach())
+        q = q0.detach().clone()
+        v = v0.detach().clone()
+        ckpt = {0: (q.clone(), v.clone())}
+        for n in range(nsteps):
+            ctx.step(q, v, p, opts)
+            if (n + 1) % checkpoint_every == 0 and n + 1 < nsteps:
+                ckpt[n + 1] = (q.clone(), v.clone())
+        fctx.ctx, fctx.params, fctx.nsteps, fctx.k, fctx.opts = ctx, p, nsteps, checkpoint_every, opts
+        fctx.ckpt = ckpt
+        fctx.save_for_backward(E)
+        fctx.vT = v.clone()
+        return q, v
+
+    @staticmethod
+    def backward(fctx, g_q, g_v):
+        ctx, p, N, k, opts = fctx.ctx, fctx.params, fctx.nsteps, fctx.k, fctx.opts
+        dev = p.E.device
+        lq = g_q.detach().to(torch.float64).contiguous().clone() if g_q is not None else \
+            torch.zeros(ctx.sizes.n_dofs, dtype=torch.float64, device=dev)
+        lv = g_v.detach().to(torch.float64).contiguous().clone() if g_v is not None else \
+            torch.zeros_like(lq)
+        dE = torch.zeros_like(p.E)
+        for s0 in reversed(range(0, N, k)):
+            s1 = min(s0 + k, N)
+            q, v = (t.clone() for t in fctx.ckpt[s0])
+            states = [(q.clone(), v.clone())]
+            for _ in range(s0, s1):
+                ctx.step(q, v, p, opts)
+                states.append((q.clone(), v.clone()))
+            for n in reversed(range(s1 - s0)):
+                qn, vn = states[n]
+                vn1 = states[n + 1][1]
+                ctx.step_adjoint(qn, vn, vn1, lq, lv, lq, lv, dE, p, opts)
+        return dE, lq, lv, None, None, None, None, None
+
+
+def rollout(E, q0, v0, ctx, params, nsteps, checkpoint_every=5, opts=None):
+    """Differentiable k-step rollout: returns (q_T, v_T)."""
+    return RolloutFn.apply(E, q0, v0, ctx, params, nsteps, checkpoint_every,
+                           opts or StepOptions())

@@ -85,7 +85,8 @@ typedef struct {
 
 typedef struct {
   int32_t leaf_nodes;         /* nested-dissection leaf size in nodes (0: 48) */
-  int32_t n_threads;          /* host factorisation threads (0: all cores)    */
+  int32_t n_threads;          /* host factorisation threads (0: the CPU share:
+                                 min(cores, OMP_NUM_THREADS, 16) - 1)         */
 } fe_build_opts;
 
 /* Physical parameters of one assembly.  E and f_nodal are DEVICE pointers. */

@@ -18,6 +18,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -680,8 +681,19 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
     c = new fe_ctx();
     c->elem_type = mesh->elem_type;
     c->nen = mesh->elem_type;
-    c->n_threads = opts && opts->n_threads > 0 ? opts->n_threads
-                                               : (int)std::max(1u, std::thread::hardware_concurrency());
+    if (opts && opts->n_threads > 0) {
+      c->n_threads = opts->n_threads;
+    } else {
+      // default: the process's CPU share (OMP_NUM_THREADS if set, else all
+      // cores, capped at 16) minus one core left to the launching thread
+      int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+      if (const char *env = getenv("OMP_NUM_THREADS")) {
+        const int v = atoi(env);
+        if (v > 0) hw = std::min(hw, v);
+      }
+      hw = std::min(hw, 16);
+      c->n_threads = std::max(1, hw - 1);
+    }
     std::string e = build_pattern(mesh->n_nodes, mesh->n_elems, c->nen, mesh->conn, fixed_dof, c->P);
     if (e.empty()) {
       // rest volume check (signed, per element)

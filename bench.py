@@ -164,13 +164,18 @@ def main():
     w = synth.make("hex_beam")
     print(f"[bench] workload hex_beam n={w.n_dofs} elems={w.n_elems}", file=sys.stderr, flush=True)
 
-    mixed = _timed_run(w, FE_PREC_MIXED, args.steps, args.warmup, timing=True)
+    mixed = _timed_run(w, FE_PREC_MIXED, args.steps, args.warmup, timing=False)
     print(f"[bench] mixed {mixed['steps_per_s']:.1f} steps/s it={mixed['cg_it_mean']:.1f}",
           file=sys.stderr, flush=True)
     sizes = mixed["sim"].ctx.sizes
-    kt = mixed["kernels"]
     mixed["sim"].ctx.close()
     del mixed["sim"]
+    # second timed region with HIP events around every launch (eager launches,
+    # same kernels) for the per-kernel durations and the roofline
+    prof = _timed_run(w, FE_PREC_MIXED, max(10, args.steps // 5), args.warmup, timing=True)
+    kt = prof["kernels"]
+    prof["sim"].ctx.close()
+    del prof["sim"]
 
     extras = {}
     if not args.no_extras:

@@ -85,6 +85,8 @@ typedef struct {
 
 typedef struct {
   int32_t leaf_nodes;         /* nested-dissection leaf size in nodes (0: 48) */
+  int32_t fwd_tile_cols;      /* forward-sweep tile width, 8..128 (0: 64)     */
+  int32_t bwd_tile_rows;      /* backward-sweep tile height, 64..1024 (0: 512)*/
   int32_t n_threads;          /* host factorisation threads (0: the CPU share:
                                  min(cores, OMP_NUM_THREADS, 16) - 1)         */
 } fe_build_opts;
@@ -253,6 +255,12 @@ int fe_precond_apply(fe_ctx *ctx, const void *A_vals, const double *r, double *z
  * (host [n_rhs * n_dofs]).  Errors: FE_EFACTOR (non-positive pivot). */
 int fe_host_factor_apply(fe_ctx *ctx, const double *A_host, const double *r_host,
                          double *z_host, int32_t n_rhs);
+
+/* CG iterations are captured once per (A, x, factor slot) into a HIP graph
+ * (kernel nodes only) and replayed on the caller's stream; enable = 0 runs
+ * every kernel with its own launch instead (also the case while kernel
+ * timing is on).  Default: enabled. */
+int fe_set_graphs(fe_ctx *ctx, int32_t enable);
 
 /* Per-kernel timing: when enabled, the library brackets every launch of the
  * triangular-solve and SpMV kernels with HIP events on the launch stream and

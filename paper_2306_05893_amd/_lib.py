@@ -42,7 +42,8 @@ class fe_mesh(C.Structure):
 
 
 class fe_build_opts(C.Structure):
-    _fields_ = [("leaf_nodes", C.c_int32), ("n_threads", C.c_int32)]
+    _fields_ = [("leaf_nodes", C.c_int32), ("fwd_tile_cols", C.c_int32),
+                ("bwd_tile_rows", C.c_int32), ("n_threads", C.c_int32)]
 
 
 class fe_params(C.Structure):
@@ -97,6 +98,7 @@ SIGNATURES = {
     "fe_spmv": (C.c_int, [_P, _P, _P, _P, _P]),
     "fe_precond_apply": (C.c_int, [_P, _P, _P, _P, _P]),
     "fe_host_factor_apply": (C.c_int, [_P, _P, _P, _P, C.c_int32]),
+    "fe_set_graphs": (C.c_int, [_P, C.c_int32]),
     "fe_set_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "fe_kernel_times": (C.c_int, [_P, _P, _P, _P, C.c_int32]),
     "fe_reset": (C.c_int, [_P]),

@@ -69,11 +69,12 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
                      const uint8_t *dof_fixed, const PcgState *state);
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
-                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state);
+                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
+                    int tile_cols);
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state);
+                    const PcgState *state, int tile_rows);
 
 // Jacobi: dinv_A[i] = 1 / A_ii ; z = dinv_A * r
 template <typename T>
@@ -81,6 +82,14 @@ void launch_diag_inv(hipStream_t st, int64_t n, const int32_t *row_ptr, const in
                      const T *val, double *dinv);
 void launch_jacobi(hipStream_t st, int64_t n, const double *dinv, const double *r, double *z,
                    const PcgState *state);
+
+// x += alpha p, r -= alpha q with ||r||^2 partials (cg_blocks(n) of them);
+// when w != NULL it also writes the sweep inputs w = r, y = 0, z = 0 (r on
+// fixed DOFs), replacing the separate preparation pass.
+template <typename T>
+void launch_update_xr_prep(hipStream_t st, int64_t n, double *x, double *r, const double *p,
+                           const double *q, double *part, const PcgState *state, T *w, T *y,
+                           double *z, const uint8_t *dof_fixed);
 
 // CG vector kernels (all no-ops once state->done is set).
 int cg_blocks(int64_t n);

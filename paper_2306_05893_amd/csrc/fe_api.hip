@@ -49,6 +49,16 @@ struct Timing {
   double bytes;
 };
 
+struct GraphKey {
+  const void *A, *x;
+  int slot, tsize;
+  bool operator==(const GraphKey &o) const {
+    return A == o.A && x == o.x && slot == o.slot && tsize == o.tsize;
+  }
+};
+
+constexpr int kGraphIters = 2;  // CG iterations per captured graph
+
 }  // namespace
 
 struct fe_ctx {
@@ -103,6 +113,11 @@ struct fe_ctx {
   int64_t installed_tag = -1;
   int64_t step_count = 0;
   bool have_prev_a = false;
+
+  // ---- graphs of CG iterations
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  std::vector<std::pair<GraphKey, hipGraphExec_t>> graphs;
 
   // ---- timing
   bool timing = false;
@@ -306,8 +321,11 @@ void factor_main(fe_ctx *c) {
 }
 
 // ------------------------------------------------------------- solve pieces
+// z = P^{-1} r.  With skip_prep the sweep inputs (w = r, y = 0, z = 0 / r on
+// fixed DOFs) were already written by the fused x/r update.
 template <typename T>
-void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, bool use_state) {
+void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, bool use_state,
+             bool skip_prep = false) {
   const int64_t n = c->P.n;
   const PcgState *s = use_state ? c->d_state : nullptr;
   if (c->active_slot < 0) {
@@ -319,17 +337,18 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
   const T *pan = (const T *)c->d_panels[slot];
   const T *dinv = (const T *)c->d_dinv[slot];
   T *w = (T *)c->d_w, *y = (T *)c->d_y;
-  launch_tri_prep<T>(st, n, r, w, y, z, c->d_dof_fixed, s);
+  if (!skip_prep) launch_tri_prep<T>(st, n, r, w, y, z, c->d_dof_fixed, s);
   const Symbolic &S = c->S;
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
-    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_sn, c->d_rows, pan, w, y, s);
+    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_sn, c->d_rows, pan, w, y, s, S.fwd_cols);
   }
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
-    launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s);
+    launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s,
+                      S.bwd_rows);
   }
 }
 
@@ -339,6 +358,55 @@ void spmv(fe_ctx *c, const T *A, const double *x, double *y, const double *w, do
   const double nnz = (double)c->P.col_idx.size(), n = (double)c->P.n;
   TimedLaunch tl(c, st, 0, nnz * (sizeof(T) + 4) + (n + 1) * 4 + n * 8 * 2);
   launch_spmv<T>(st, c->P.n, c->spmv_lanes, c->d_row_ptr, c->d_col, A, x, y, w, part, np, s);
+}
+
+// One CG iteration: q = A p with alpha; x, r update (+ sweep inputs); z = P^{-1} r;
+// beta; p = z + beta p.  Every kernel returns at once when the done flag is set.
+template <typename T>
+void cg_iteration(fe_ctx *c, const T *A, double *x, hipStream_t st) {
+  const int64_t n = c->P.n;
+  const bool tri = c->active_slot >= 0;
+  int np = 0;
+  spmv<T>(c, A, c->d_p, c->d_q, c->d_p, c->d_part1, &np, st, c->d_state);
+  launch_ctl_alpha(st, c->d_state, c->d_part1, np);
+  launch_update_xr_prep<T>(st, n, x, c->d_r, c->d_p, c->d_q, c->d_part2, c->d_state,
+                           tri ? (T *)c->d_w : nullptr, (T *)c->d_y, c->d_z, c->d_dof_fixed);
+  launch_ctl_rr(st, c->d_state, c->d_part2, cg_blocks(n));
+  precond<T>(c, A, c->d_r, c->d_z, st, true, tri);
+  launch_dot(st, n, c->d_r, c->d_z, c->d_part1, c->d_state);
+  launch_ctl_rz(st, c->d_state, c->d_part1, cg_blocks(n), 0);
+  launch_update_p(st, n, c->d_p, c->d_z, c->d_state, 0);
+}
+
+// A HIP graph of kGraphIters CG iterations for (A, x, factor slot), captured
+// on the context's private stream and replayed on the caller's stream.  The
+// graph holds kernel nodes only (no memset/copy nodes).
+template <typename T>
+hipGraphExec_t iter_graph(fe_ctx *c, const T *A, double *x) {
+  const GraphKey key{(const void *)A, (const void *)x, c->active_slot, (int)sizeof(T)};
+  for (auto &kv : c->graphs)
+    if (kv.first == key) return kv.second;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->use_graphs = false;
+    return nullptr;
+  }
+  for (int k = 0; k < kGraphIters; ++k) cg_iteration<T>(c, A, x, c->cap_stream);
+  if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !g ||
+      hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    c->use_graphs = false;
+    return nullptr;
+  }
+  (void)hipGraphDestroy(g);
+  if (c->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(c->graphs.front().second);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({key, ex});
+  return ex;
 }
 
 int read_state(fe_ctx *c, hipStream_t st) {
@@ -363,6 +431,7 @@ int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_i
   spmv<T>(c, A, x, c->d_tmp, nullptr, nullptr, nullptr, st, nullptr);
   launch_residual(st, n, b, c->d_tmp, c->d_r, c->d_part1, c->d_part2);
   launch_ctl_init(st, c->d_state, c->d_part1, c->d_part2, nb, tol);
+  (void)np;
   auto restart = [&]() {
     precond<T>(c, A, c->d_r, c->d_z, st, true);
     launch_dot(st, n, c->d_r, c->d_z, c->d_part1, c->d_state);
@@ -375,15 +444,14 @@ int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_i
   int restarts = 0;
   int32_t last_it = -1;
   for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      spmv<T>(c, A, c->d_p, c->d_q, c->d_p, c->d_part1, &np, st, c->d_state);
-      launch_ctl_alpha(st, c->d_state, c->d_part1, np);
-      launch_update_xr(st, n, x, c->d_r, c->d_p, c->d_q, c->d_part2, c->d_state);
-      launch_ctl_rr(st, c->d_state, c->d_part2, nb);
-      precond<T>(c, A, c->d_r, c->d_z, st, true);
-      launch_dot(st, n, c->d_r, c->d_z, c->d_part1, c->d_state);
-      launch_ctl_rz(st, c->d_state, c->d_part1, nb, 0);
-      launch_update_p(st, n, c->d_p, c->d_z, c->d_state, 0);
+    hipGraphExec_t g = c->use_graphs && !c->timing ? iter_graph<T>(c, A, x) : nullptr;
+    if (g) {
+      for (int k = 0; k < chunk; k += kGraphIters) {
+        hipError_t e = hipGraphLaunch(g, st);
+        if (e != hipSuccess) return c->fail(FE_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+      }
+    } else {
+      for (int k = 0; k < chunk; ++k) cg_iteration<T>(c, A, x, st);
     }
     {
       hipError_t le = hipGetLastError();
@@ -431,6 +499,7 @@ int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_i
     chunk = std::min(16, std::max(2, chunk * 2));
     chunk = std::min(chunk, max_it - h.it);
     if (chunk <= 0) chunk = 1;
+    chunk = (chunk + kGraphIters - 1) / kGraphIters * kGraphIters;
   }
   if (out) {
     out->iterations = c->h_state->it;
@@ -659,6 +728,8 @@ fe_ctx::~fe_ctx() {
                          ev_slot_free[1]})
       if (e) (void)hipEventDestroy(e);
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 }
 
@@ -715,7 +786,8 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
     }
     if (e.empty()) {
       c->X.assign(mesh->X, mesh->X + 3 * (int64_t)mesh->n_nodes);
-      e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, c->S);
+      e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, opts ? opts->fwd_tile_cols : 0,
+                  opts ? opts->bwd_tile_rows : 0, c->S);
     }
     if (!e.empty()) {
       g_build_error = e;
@@ -817,6 +889,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
                         std::max<size_t>(1, (c->S.panel_entries + c->P.n) * c->tsize),
                         hipHostMallocDefault));
   HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_snap_ready, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_snap_done, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_upload_done, hipEventDisableTiming));
@@ -1050,6 +1123,12 @@ int fe_host_factor_apply(fe_ctx *c, const double *A_host, const double *r_host, 
       }
     }
   }
+  return FE_OK;
+}
+
+int fe_set_graphs(fe_ctx *c, int32_t enable) {
+  if (!c) return FE_EINVAL;
+  c->use_graphs = enable != 0;
   return FE_OK;
 }
 

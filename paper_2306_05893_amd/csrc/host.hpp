@@ -66,17 +66,19 @@ struct Symbolic {
   // GPU schedules, grouped by level (forward: ascending, backward: descending)
   std::vector<Tile> fwd_tiles, bwd_tiles;
   std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
+  int32_t fwd_cols = 0, bwd_rows = 0;  // tile extents in use
 };
 
 // Tile extents shared with the device kernels.
-constexpr int kFwdRows = 256;   // rows per forward tile (one per thread)
-constexpr int kFwdCols = 128;   // columns per forward tile
-constexpr int kBwdCols = 16;    // columns per backward tile
-constexpr int kBwdRows = 1024;  // rows per backward tile
+constexpr int kFwdRows = 256;      // rows per forward tile (one per thread)
+constexpr int kFwdColsMax = 128;   // columns per forward tile: 8..128 (option)
+constexpr int kBwdCols = 16;       // columns per backward tile (4 per wavefront)
+constexpr int kBwdRowsMax = 1024;  // rows per backward tile: 64..1024 (option)
 
 // Geometric nested dissection on the node graph, supernodes = ND blocks,
 // relaxed (dense) supernodal structure from the assembly tree.
-std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, Symbolic &S);
+std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
+                    int32_t bwd_rows, Symbolic &S);
 
 // ------------------------------------------------------- numeric factor
 // Parallel-for helper (dynamic scheduling on std::threads).

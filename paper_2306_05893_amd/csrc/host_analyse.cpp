@@ -147,8 +147,13 @@ struct Dissector {
 
 }  // namespace
 
-std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, Symbolic &S) {
+std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
+                    int32_t bwd_rows, Symbolic &S) {
   if (leaf_nodes <= 0) leaf_nodes = 48;
+  if (fwd_cols <= 0) fwd_cols = 64;
+  if (bwd_rows <= 0) bwd_rows = 512;
+  if (fwd_cols < 8 || fwd_cols > kFwdColsMax || bwd_rows < 64 || bwd_rows > kBwdRowsMax)
+    return "tile extents out of range";
   const int32_t N = P.n_nodes;
   S = Symbolic();
   S.n = P.n;
@@ -305,7 +310,7 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, Symbo
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
       for (int32_t r0 = 0; r0 < sn.m; r0 += kFwdRows)
-        for (int32_t c0 = 0; c0 < sn.nc; c0 += kFwdCols) {
+        for (int32_t c0 = 0; c0 < sn.nc; c0 += fwd_cols) {
           const int32_t r1 = std::min(sn.m, r0 + kFwdRows);
           if (r1 <= c0) continue;  // entirely above the diagonal of L11^{-1}
           S.fwd_tiles.push_back({s, r0, c0, 0});
@@ -317,14 +322,16 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, Symbo
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
       for (int32_t c0 = 0; c0 < sn.nc; c0 += kBwdCols)
-        for (int32_t r0 = 0; r0 < sn.m; r0 += kBwdRows) {
-          const int32_t r1 = std::min(sn.m, r0 + kBwdRows);
+        for (int32_t r0 = 0; r0 < sn.m; r0 += bwd_rows) {
+          const int32_t r1 = std::min(sn.m, r0 + bwd_rows);
           if (r1 <= c0) continue;
           S.bwd_tiles.push_back({s, r0, c0, 0});
         }
     }
     S.bwd_level_ptr.push_back((int32_t)S.bwd_tiles.size());
   }
+  S.fwd_cols = fwd_cols;
+  S.bwd_rows = bwd_rows;
   return "";
 }
 

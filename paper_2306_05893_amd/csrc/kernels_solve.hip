@@ -183,6 +183,34 @@ __global__ __launch_bounds__(kBlock) void k_update_p(int64_t n, double *p, const
   if (i < n) p[i] = first ? z[i] : z[i] + s->beta * p[i];
 }
 
+// x += alpha p, r -= alpha q with per-block ||r||^2 partials; when w is
+// given it also writes the sweep inputs (w = r, y = 0, z = 0 or r on fixed
+// DOFs), saving the separate preparation pass.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update_xr_prep(int64_t n, double *x, double *r,
+                                                           const double *p, const double *q,
+                                                           double *part, const PcgState *s,
+                                                           T *w, T *y, double *z,
+                                                           const uint8_t *fixed) {
+  if (s->done) return;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const double al = s->alpha;
+  double rr = 0.0;
+  if (i < n) {
+    x[i] += al * p[i];
+    const double ri = r[i] - al * q[i];
+    r[i] = ri;
+    rr = ri * ri;
+    if (w) {
+      w[i] = (T)ri;
+      y[i] = T(0);
+      z[i] = fixed[i] ? ri : 0.0;
+    }
+  }
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
 __global__ void k_zero(int64_t n, double *x) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) x[i] = 0.0;
@@ -230,49 +258,58 @@ __global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
   z[i] = fixed[i] ? ri : 0.0;
 }
 
-constexpr int kFR = 256, kFC = 128;   // forward tile: rows x columns
-constexpr int kBC = 16, kBR = 1024;   // backward tile: columns x rows
+constexpr int kFR = 256, kFCmax = 128;   // forward tile: 256 rows x (8..128) columns
+constexpr int kBC = 16, kBRmax = 1024;   // backward tile: 16 columns x (64..1024) rows
 
 // Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
-// rows; own rows (i < nc) accumulate into y, struct rows subtract from w.
+// rows (one row per thread, consecutive rows = consecutive addresses of the
+// column-major panel); own rows (i < nc) accumulate into y, struct rows
+// subtract from w.  Entries above the diagonal of L11^{-1} are skipped.
 template <typename T>
 __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
                                                  const SnDev *__restrict__ sn,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels, T *w, T *y,
-                                                 const PcgState *s) {
+                                                 const PcgState *s, int TC) {
   if (s && s->done) return;
-  __shared__ T s_in[kFC];
+  __shared__ T s_in[kFCmax];
   const TileDev t = tiles[blockIdx.x];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
-  const int c0 = t.c0, c1 = min(d.nc, c0 + kFC);
+  const int c0 = t.c0, c1 = min(d.nc, c0 + TC);
   if ((int)threadIdx.x < c1 - c0) s_in[threadIdx.x] = w[rw[c0 + threadIdx.x]];
   __syncthreads();
   const int i = t.r0 + (int)threadIdx.x;
   if (i >= d.m) return;
-  const int jend = (i < d.nc) ? min(c1, i + 1) : c1;
-  if (jend <= c0) return;
-  const T *G = panels + d.panel_off + (int64_t)c0 * d.m + i;
-  T acc = T(0);
-  int j = c0;
-  for (; j + 4 <= jend; j += 4) {
-    acc += G[0] * s_in[j - c0];
-    acc += G[(int64_t)d.m] * s_in[j + 1 - c0];
-    acc += G[2 * (int64_t)d.m] * s_in[j + 2 - c0];
-    acc += G[3 * (int64_t)d.m] * s_in[j + 3 - c0];
-    G += 4 * (int64_t)d.m;
+  const int cnt = ((i < d.nc) ? min(c1, i + 1) : c1) - c0;
+  if (cnt <= 0) return;
+  const int64_t m = d.m;
+  const T *G = panels + d.panel_off + (int64_t)c0 * m + i;
+  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+  int j = 0;
+  for (; j + 8 <= cnt; j += 8) {
+    const T g0 = G[0], g1 = G[m], g2 = G[2 * m], g3 = G[3 * m];
+    const T g4 = G[4 * m], g5 = G[5 * m], g6 = G[6 * m], g7 = G[7 * m];
+    a0 += g0 * s_in[j] + g4 * s_in[j + 4];
+    a1 += g1 * s_in[j + 1] + g5 * s_in[j + 5];
+    a2 += g2 * s_in[j + 2] + g6 * s_in[j + 6];
+    a3 += g3 * s_in[j + 3] + g7 * s_in[j + 7];
+    G += 8 * m;
   }
-  for (; j < jend; ++j) {
-    acc += G[0] * s_in[j - c0];
-    G += d.m;
+  for (; j < cnt; ++j) {
+    a0 += G[0] * s_in[j];
+    G += m;
   }
+  const T acc = (a0 + a1) + (a2 + a3);
   if (i < d.nc) atomicAdd(y + rw[i], acc);
   else atomicAdd(w + rw[i], -acc);
 }
 
 // Backward tile: x[rows[j]] += sum_{i in tile rows} G[i, j] v_i with
 // v_i = dinv y (own rows) or -x[rows[i]] (struct rows, already final).
+// Each wavefront handles 4 consecutive columns, loading the 4 column
+// segments together (lanes stride over rows); rows above a column's diagonal
+// hold explicit zeros in the panel, so no masking is needed past max(r0, j0).
 template <typename T>
 __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
                                                  const SnDev *__restrict__ sn,
@@ -280,13 +317,13 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
                                                  const T *__restrict__ panels,
                                                  const T *__restrict__ dinv,
                                                  const T *__restrict__ y, double *z,
-                                                 const PcgState *s) {
+                                                 const PcgState *s, int BR) {
   if (s && s->done) return;
-  __shared__ T s_v[kBR];
+  __shared__ T s_v[kBRmax];
   const TileDev t = tiles[blockIdx.x];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
-  const int r0 = t.r0, r1 = min(d.m, r0 + kBR);
+  const int r0 = t.r0, r1 = min(d.m, r0 + BR);
   for (int k = threadIdx.x; k < r1 - r0; k += 256) {
     const int i = r0 + k;
     const int32_t dof = rw[i];
@@ -294,16 +331,38 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int cc = 0; cc < kBC / 4; ++cc) {
-    const int j = t.c0 + wv * (kBC / 4) + cc;
-    if (j >= d.nc) break;
-    const int ibeg = max(r0, j);
-    const T *G = panels + d.panel_off + (int64_t)j * d.m;
-    double acc = 0.0;
-    T part = T(0);
-    for (int i = ibeg + lane; i < r1; i += 64) part += G[i] * s_v[i - r0];
-    acc = wave_sum((double)part);
-    if (lane == 0 && ibeg < r1) atomicAdd(z + rw[j], acc);
+  const int j0 = t.c0 + 4 * wv;
+  if (j0 >= d.nc) return;
+  const int nj = min(4, d.nc - j0);
+  const int ibeg = max(r0, j0);
+  if (ibeg >= r1) return;
+  const int64_t m = d.m;
+  const T *G = panels + d.panel_off + (int64_t)j0 * m;
+  T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
+  if (nj == 4) {
+    for (int i = ibeg + lane; i < r1; i += 64) {
+      const T v = s_v[i - r0];
+      const T g0 = G[i], g1 = G[m + i], g2 = G[2 * m + i], g3 = G[3 * m + i];
+      p0 += g0 * v;
+      p1 += g1 * v;
+      p2 += g2 * v;
+      p3 += g3 * v;
+    }
+  } else {
+    for (int i = ibeg + lane; i < r1; i += 64) {
+      const T v = s_v[i - r0];
+      p0 += G[i] * v;
+      if (nj > 1) p1 += G[m + i] * v;
+      if (nj > 2) p2 += G[2 * m + i] * v;
+    }
+  }
+  const double q0 = wave_sum((double)p0), q1 = wave_sum((double)p1);
+  const double q2 = wave_sum((double)p2), q3 = wave_sum((double)p3);
+  if (lane == 0) {
+    atomicAdd(z + rw[j0], q0);
+    if (nj > 1) atomicAdd(z + rw[j0 + 1], q1);
+    if (nj > 2) atomicAdd(z + rw[j0 + 2], q2);
+    if (nj > 3) atomicAdd(z + rw[j0 + 3], q3);
   }
 }
 
@@ -332,6 +391,14 @@ void launch_spmv(hipStream_t st, int64_t n, int G, const int32_t *row_ptr, const
 }
 
 int cg_blocks(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+template <typename T>
+void launch_update_xr_prep(hipStream_t st, int64_t n, double *x, double *r, const double *p,
+                           const double *q, double *part, const PcgState *s, T *w, T *y, double *z,
+                           const uint8_t *fixed) {
+  k_update_xr_prep<T><<<cg_blocks(n), kBlock, 0, st>>>(n, x, r, p, q, part, s, w, y, z, fixed);
+}
+
 
 void launch_residual(hipStream_t st, int64_t n, const double *b, const double *Ax, double *r,
                      double *prr, double *pbb) {
@@ -390,30 +457,36 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
 }
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
-                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state) {
-  if (n_tiles > 0) k_tri_fwd<T><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state);
+                    const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
+                    int tile_cols) {
+  if (n_tiles > 0)
+    k_tri_fwd<T><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state, tile_cols);
 }
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state) {
+                    const PcgState *state, int tile_rows) {
   if (n_tiles > 0)
-    k_tri_bwd<T><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+    k_tri_bwd<T><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state, tile_rows);
 }
 
 #define FE_INST(T)                                                                             \
   template void launch_spmv<T>(hipStream_t, int64_t, int, const int32_t *, const int32_t *,    \
                                const T *, const double *, double *, const double *, double *,  \
                                int *, const PcgState *);                                       \
+  template void launch_update_xr_prep<T>(hipStream_t, int64_t, double *, double *,             \
+                                         const double *, const double *, double *,             \
+                                         const PcgState *,                                     \
+                                         T *, T *, double *, const uint8_t *);                 \
   template void launch_diag_inv<T>(hipStream_t, int64_t, const int32_t *, const int32_t *,     \
                                    const T *, double *);                                       \
   template void launch_tri_prep<T>(hipStream_t, int64_t, const double *, T *, T *, double *,   \
                                    const uint8_t *, const PcgState *);                         \
   template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
-                                  const int32_t *, const T *, T *, T *, const PcgState *);     \
+                                  const int32_t *, const T *, T *, T *, const PcgState *, int);\
   template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
                                   const int32_t *, const T *, const T *, const T *, double *,  \
-                                  const PcgState *);
+                                  const PcgState *, int);
 FE_INST(float)
 FE_INST(double)
 #undef FE_INST

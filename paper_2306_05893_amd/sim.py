@@ -78,7 +78,7 @@ class FEContext:
     """One library context bound to a caller-owned torch workspace."""
 
     def __init__(self, X, conn, elem_type, fixed=None, prec=L.FE_PREC_FP64, leaf_nodes=0,
-                 n_threads=0, device="cuda"):
+                 n_threads=0, device="cuda", fwd_tile_cols=0, bwd_tile_rows=0):
         self.lib = L.load()
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1)
         conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1)
@@ -91,7 +91,8 @@ class FEContext:
         if fixed is not None:
             fixed = np.ascontiguousarray(fixed, dtype=np.uint8).reshape(-1)
             fx = fixed.ctypes.data_as(C.c_void_p)
-        opts = L.fe_build_opts(int(leaf_nodes), int(n_threads))
+        opts = L.fe_build_opts(int(leaf_nodes), int(fwd_tile_cols), int(bwd_tile_rows),
+                               int(n_threads))
         h = C.c_void_p()
         L.check(self.lib.fe_build_pattern(C.byref(mesh), fx, C.byref(opts), C.byref(h)), None)
         self.h = h
@@ -286,6 +287,9 @@ class FEContext:
             self._vals(A)
         self._chk(self.lib.fe_precond_apply(self.h, _ptr(A), _ptr(r), _ptr(z), _stream()))
         return z
+
+    def set_graphs(self, on=True):
+        self._chk(self.lib.fe_set_graphs(self.h, 1 if on else 0))
 
     def set_kernel_timing(self, on=True):
         self._chk(self.lib.fe_set_kernel_timing(self.h, 1 if on else 0))

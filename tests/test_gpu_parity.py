@@ -159,6 +159,37 @@ def test_pcg_residual_certificate(mesh, prec, use_factor):
         assert st.iterations <= 2          # exact preconditioner
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("use_factor", [True, False])
+def test_graph_replays_match_eager(prec, use_factor):
+    """CG iterations replayed from a captured HIP graph give the eager result
+    on every replay (stale factor: several iterations per solve), with eager
+    library work and host synchronisation between the replays."""
+    w = synth.make("hex_diff")
+    ctx = _ctx(w, prec)
+    p = _params(w)
+    if use_factor:
+        A0, _ = ctx.assemble(p, _t(w.q0()), _t(w.v0()))
+        ctx.factorize_now(A0, 0)
+    q, v = _state(w, steps=4)
+    A, b = ctx.assemble(p, _t(q), _t(v))
+    runs = []
+    for mode in ["eager", "graph", "graph", "eager", "graph", "graph"]:
+        ctx.set_graphs(mode == "graph")
+        x, st = ctx.pcg_solve(A, b, rel_tol=1e-10, max_it=3000)
+        torch.cuda.synchronize()
+        runs.append((mode, x.cpu().numpy(), st.iterations, st.rel_res))
+        ctx.spmv(A, x)                         # eager work between replays
+        torch.cuda.synchronize()
+    ref = runs[0]
+    print("  " + ", ".join(f"{m}:{it}" for m, _, it, _ in runs))
+    assert ref[2] > 2
+    for mode, x, it, rr in runs[1:]:
+        assert abs(it - ref[2]) <= 2, (mode, it, ref[2])
+        assert rr <= 1e-10 * 1.01
+        assert _rel(x, ref[1]) <= 1e-7
+
+
 def test_zero_rhs_gives_zero_solution():
     w = synth.make("tiny_hex")
     ctx = _ctx(w, 0)

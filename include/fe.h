@@ -87,6 +87,10 @@ typedef struct {
   int32_t leaf_nodes;         /* nested-dissection leaf size in nodes (0: 48) */
   int32_t fwd_tile_cols;      /* forward-sweep tile width, 8..128 (0: 64)     */
   int32_t bwd_tile_rows;      /* backward-sweep tile height, 64..1024 (0: 512)*/
+  int32_t factor_on_gpu;      /* 1: fe_factor_async runs the FP64 multifrontal
+                                 LDL^T on the GPU (own stream, writes the idle
+                                 factor slot directly; no host round trip);
+                                 0: host factor thread (the paper's scheme)  */
   int32_t n_threads;          /* host factorisation threads (0: the CPU share:
                                  min(cores, OMP_NUM_THREADS, 16) - 1)         */
 } fe_build_opts;

@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+
+#include "host.hpp"
 
 namespace fe {
 
@@ -110,6 +113,26 @@ void launch_ctl_true(hipStream_t st, PcgState *s, const double *part, int np);
 void launch_zero(hipStream_t st, int64_t n, double *x);
 void launch_integrate(hipStream_t st, int64_t n, double h, const double *a, double *q,
                       double *v);
+
+// GPU factorisation: device copies of the GfPlan arrays plus the front store.
+struct GfDev {
+  const GfFront *fr;
+  const int32_t *lvl_sn, *a_csr;
+  const int64_t *a_off;
+  const int32_t *parent, *rel;
+  const int64_t *rel_off;
+  const GfExt *ext;
+  const int32_t *panel_sn;
+  const GfTile *upd;
+  const int32_t *rows;
+  double *fronts;
+  int *status;          // bit 0: non-positive pivot met
+};
+// FP64 multifrontal LDL^T of A (values TA) -> explicit-inverse panels and
+// 1/d (T), queued on st.  The plan's host arrays drive the launch sequence.
+template <typename TA, typename T>
+void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA *A, T *panels,
+                       T *dinv);
 
 // Adjoint element pass: lam_q_out, lam_v_out, dE (see fe.h fe_step_adjoint)
 template <typename T>

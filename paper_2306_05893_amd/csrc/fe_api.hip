@@ -21,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -114,6 +115,18 @@ struct fe_ctx {
   int64_t step_count = 0;
   bool have_prev_a = false;
 
+  // ---- GPU factorisation (factor_on_gpu)
+  bool gpu_factor = false;
+  GfPlan G;
+  GfDev gd{};
+  void *d_Asnap = nullptr;
+  int *h_gf_status = nullptr;
+  hipStream_t factor_stream = nullptr;
+  hipEvent_t ev_gf_done = nullptr;
+  bool gf_pending = false;
+  int64_t gf_tag = -1;
+  int gf_slot = -1, ready_slot = -1;
+
   // ---- graphs of CG iterations
   bool use_graphs = true;
   hipStream_t cap_stream = nullptr;
@@ -143,11 +156,13 @@ namespace {
 
 // ------------------------------------------------------------- layout
 struct Layout {
-  int64_t off[40];
+  static constexpr int kMax = 64;
+  int64_t off[kMax];
   int64_t total = 0;
   int k = 0;
   int64_t add(int64_t bytes) {
     const int64_t o = total;
+    if (k >= kMax) throw std::runtime_error("workspace layout: too many sections");
     off[k++] = o;
     total += (bytes + 255) / 256 * 256;
     return o;
@@ -157,7 +172,9 @@ struct Layout {
 enum {
   L_ROWPTR, L_COL, L_CONN, L_SLOT, L_SMAP, L_FDS, L_DOFFIX, L_X, L_SN, L_ROWS, L_FT, L_BT,
   L_PAN0, L_PAN1, L_DINV0, L_DINV1, L_JDINV, L_R, L_Z, L_P, L_Q, L_TMP, L_B, L_ACC, L_ABAR,
-  L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE
+  L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
+  L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
+  L_GF_UPD, L_GF_ASNAP, L_GF_STATUS
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -192,6 +209,21 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(std::max(np, spmv_parts) * 8);
   L.add(std::max(np, spmv_parts) * 8);
   L.add(256);
+  const bool g = c->gpu_factor;
+  const GfPlan &Gp = c->G;
+  L.add(g ? Gp.doubles * 8 : 0);
+  L.add(g ? (int64_t)Gp.fr.size() * (int64_t)sizeof(GfFront) : 0);
+  L.add(g ? (int64_t)Gp.lvl_sn.size() * 4 : 0);
+  L.add(g ? (int64_t)Gp.a_csr.size() * 4 : 0);
+  L.add(g ? (int64_t)Gp.a_off.size() * 8 : 0);
+  L.add(g ? (int64_t)Gp.parent.size() * 4 : 0);
+  L.add(g ? (int64_t)Gp.rel.size() * 4 : 0);
+  L.add(g ? (int64_t)Gp.rel_off.size() * 8 : 0);
+  L.add(g ? (int64_t)Gp.ext.size() * (int64_t)sizeof(GfExt) : 0);
+  L.add(g ? (int64_t)Gp.panel_sn.size() * 4 : 0);
+  L.add(g ? (int64_t)Gp.upd.size() * (int64_t)sizeof(GfTile) : 0);
+  L.add(g ? nnz * ts : 0);
+  L.add(g ? 256 : 0);
   return L;
 }
 
@@ -551,7 +583,46 @@ int clear_elem_status(fe_ctx *c, hipStream_t st) {
   return FE_OK;
 }
 
+// ---- GPU factorisation job bookkeeping (caller holds c->mu)
+int gf_collect_locked(fe_ctx *c, bool block) {
+  if (!c->gf_pending) return FE_OK;
+  if (!block && hipEventQuery(c->ev_gf_done) == hipErrorNotReady) return FE_OK;
+  HIP_TRY(hipEventSynchronize(c->ev_gf_done));
+  HIP_TRY(hipMemcpyAsync(c->h_gf_status, c->gd.status, sizeof(int), hipMemcpyDeviceToHost,
+                         c->factor_stream));
+  HIP_TRY(hipStreamSynchronize(c->factor_stream));
+  c->gf_pending = false;
+  if (*c->h_gf_status) {
+    c->job_status = FE_EFACTOR;
+    c->job_err = "non-positive pivot in the GPU LDL^T";
+  } else {
+    c->job_status = FE_OK;
+    c->job_err.clear();
+    c->ready_tag = c->gf_tag;
+    c->ready_slot = c->gf_slot;
+  }
+  return FE_OK;
+}
+
+bool factor_busy_locked(fe_ctx *c) {
+  if (c->gpu_factor) {
+    (void)gf_collect_locked(c, false);
+    return c->gf_pending;
+  }
+  return c->job_pending || c->job_running;
+}
+
 int install_locked(fe_ctx *c, hipStream_t st) {
+  if (c->gpu_factor) {
+    int rc = gf_collect_locked(c, false);
+    if (rc) return rc;
+    if (c->ready_tag < 0 || c->ready_tag == c->installed_tag || c->ready_slot < 0) return FE_OK;
+    HIP_TRY(hipStreamWaitEvent(st, c->ev_gf_done, 0));
+    if (c->active_slot >= 0) HIP_TRY(hipEventRecord(c->ev_slot_free[c->active_slot], st));
+    c->active_slot = c->ready_slot;
+    c->installed_tag = c->ready_tag;
+    return FE_OK;
+  }
   if (c->ready_tag < 0 || c->ready_tag == c->installed_tag) return FE_OK;
   const int slot = c->active_slot < 0 ? 0 : 1 - c->active_slot;
   const size_t pan_bytes = (size_t)c->S.panel_entries * c->tsize;
@@ -570,9 +641,36 @@ int install_locked(fe_ctx *c, hipStream_t st) {
   return FE_OK;
 }
 
+// GPU job: snapshot A on the factor stream (after the work queued on st),
+// then factor into the idle slot once the solves that used it are done.
+int gf_start_locked(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
+  const int slot = c->active_slot < 0 ? 0 : 1 - c->active_slot;
+  if (c->ready_slot == slot) c->ready_tag = c->installed_tag;  // superseded
+  c->ready_slot = -1;
+  HIP_TRY(hipEventRecord(c->ev_snap_ready, st));
+  HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_snap_ready, 0));
+  HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_slot_free[slot], 0));
+  HIP_TRY(hipMemcpyAsync(c->d_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToDevice,
+                         c->factor_stream));
+  HIP_TRY(hipMemsetAsync(c->gd.status, 0, sizeof(int), c->factor_stream));
+  if (c->prec == FE_PREC_MIXED)
+    launch_gpu_factor<float, float>(c->factor_stream, c->G, c->gd, (const float *)c->d_Asnap,
+                                    (float *)c->d_panels[slot], (float *)c->d_dinv[slot]);
+  else
+    launch_gpu_factor<double, double>(c->factor_stream, c->G, c->gd, (const double *)c->d_Asnap,
+                                      (double *)c->d_panels[slot], (double *)c->d_dinv[slot]);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(c->ev_gf_done, c->factor_stream));
+  c->gf_pending = true;
+  c->gf_tag = tag;
+  c->gf_slot = slot;
+  return FE_OK;
+}
+
 int factor_async_impl(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   std::unique_lock<std::mutex> lk(c->mu);
-  if (c->job_pending || c->job_running) return c->fail(FE_EBUSY, "factorisation in progress");
+  if (factor_busy_locked(c)) return c->fail(FE_EBUSY, "factorisation in progress");
+  if (c->gpu_factor) return gf_start_locked(c, A, tag, st);
   HIP_TRY(hipEventRecord(c->ev_snap_ready, st));
   HIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_snap_ready, 0));
   HIP_TRY(hipMemcpyAsync(c->h_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToHost,
@@ -586,7 +684,12 @@ int factor_async_impl(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
 
 int factor_wait_impl(fe_ctx *c, int64_t tag) {
   std::unique_lock<std::mutex> lk(c->mu);
-  c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+  if (c->gpu_factor) {
+    int rc = gf_collect_locked(c, true);
+    if (rc) return rc;
+  } else {
+    c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+  }
   if (c->job_status != FE_OK) return c->fail(c->job_status, "%s", c->job_err.c_str());
   if (c->ready_tag < tag) return c->fail(FE_ESTATE, "no factorisation job with tag %lld",
                                          (long long)tag);
@@ -606,11 +709,11 @@ int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step
     bool busy;
     {
       std::lock_guard<std::mutex> lk(c->mu);
-      busy = c->job_pending || c->job_running;
+      busy = factor_busy_locked(c);
     }
     if (busy && o->mode == FE_FACTOR_DETERMINISTIC) {
-      std::unique_lock<std::mutex> lk(c->mu);
-      c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+      rc = factor_wait_impl(c, -1);
+      if (rc) return rc;
       busy = false;
     }
     if (!busy) {
@@ -730,6 +833,12 @@ fe_ctx::~fe_ctx() {
     if (copy_stream) (void)hipStreamDestroy(copy_stream);
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (factor_stream) {
+      (void)hipStreamSynchronize(factor_stream);
+      (void)hipStreamDestroy(factor_stream);
+    }
+    if (ev_gf_done) (void)hipEventDestroy(ev_gf_done);
+    if (h_gf_status) (void)hipHostFree(h_gf_status);
   }
 }
 
@@ -789,6 +898,10 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
       e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, opts ? opts->fwd_tile_cols : 0,
                   opts ? opts->bwd_tile_rows : 0, c->S);
     }
+    if (e.empty() && opts && opts->factor_on_gpu) {
+      c->gpu_factor = true;
+      e = gpu_plan(c->P, c->S, c->G);
+    }
     if (!e.empty()) {
       g_build_error = e;
       delete c;
@@ -812,7 +925,12 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
 int fe_query(fe_ctx *c, int32_t prec, fe_sizes *o) {
   if (!c || !o) return FE_EINVAL;
   if (prec != FE_PREC_FP64 && prec != FE_PREC_MIXED) return c->fail(FE_EINVAL, "bad precision");
-  const Layout L = make_layout(c, prec);
+  Layout L;
+  try {
+    L = make_layout(c, prec);
+  } catch (const std::exception &ex) {
+    return c->fail(FE_EINVAL, "%s", ex.what());
+  }
   o->n_dofs = c->P.n;
   o->nnz = (int64_t)c->P.col_idx.size();
   o->n_elems = c->P.n_elems;
@@ -832,7 +950,12 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   if (!c) return FE_EINVAL;
   if (c->bound) return c->fail(FE_ESTATE, "context already bound");
   if (prec != FE_PREC_FP64 && prec != FE_PREC_MIXED) return c->fail(FE_EINVAL, "bad precision");
-  const Layout L = make_layout(c, prec);
+  Layout L;
+  try {
+    L = make_layout(c, prec);
+  } catch (const std::exception &ex) {
+    return c->fail(FE_EINVAL, "%s", ex.what());
+  }
   if (!d_ws || ws_bytes < L.total)
     return c->fail(FE_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)ws_bytes,
                    (long long)L.total);
@@ -936,6 +1059,49 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
     c->fwd_level_bytes[s.level] += bytes;
     c->bwd_level_bytes[S.n_levels - 1 - s.level] += bytes;
   }
+  if (c->gpu_factor) {
+    GfDev &g = c->gd;
+    const GfPlan &Gp = c->G;
+    g.fronts = ptr_at<double>(w, L, L_GF_FRONTS);
+    GfFront *fr = ptr_at<GfFront>(w, L, L_GF_FR);
+    int32_t *lvl_sn = ptr_at<int32_t>(w, L, L_GF_LVLSN);
+    int32_t *a_csr = ptr_at<int32_t>(w, L, L_GF_ACSR);
+    int64_t *a_off = ptr_at<int64_t>(w, L, L_GF_AOFF);
+    int32_t *parent = ptr_at<int32_t>(w, L, L_GF_PARENT);
+    int32_t *rel = ptr_at<int32_t>(w, L, L_GF_REL);
+    int64_t *rel_off = ptr_at<int64_t>(w, L, L_GF_RELOFF);
+    GfExt *ext = ptr_at<GfExt>(w, L, L_GF_EXT);
+    int32_t *panel_sn = ptr_at<int32_t>(w, L, L_GF_PANELSN);
+    GfTile *upd = ptr_at<GfTile>(w, L, L_GF_UPD);
+    HIP_TRY(up(fr, Gp.fr.data(), Gp.fr.size() * sizeof(GfFront)));
+    HIP_TRY(up(lvl_sn, Gp.lvl_sn.data(), Gp.lvl_sn.size() * 4));
+    HIP_TRY(up(a_csr, Gp.a_csr.data(), Gp.a_csr.size() * 4));
+    HIP_TRY(up(a_off, Gp.a_off.data(), Gp.a_off.size() * 8));
+    HIP_TRY(up(parent, Gp.parent.data(), Gp.parent.size() * 4));
+    HIP_TRY(up(rel, Gp.rel.data(), Gp.rel.size() * 4));
+    HIP_TRY(up(rel_off, Gp.rel_off.data(), Gp.rel_off.size() * 8));
+    HIP_TRY(up(ext, Gp.ext.data(), Gp.ext.size() * sizeof(GfExt)));
+    HIP_TRY(up(panel_sn, Gp.panel_sn.data(), Gp.panel_sn.size() * 4));
+    HIP_TRY(up(upd, Gp.upd.data(), Gp.upd.size() * sizeof(GfTile)));
+    HIP_TRY(hipStreamSynchronize(st));
+    g.fr = fr;
+    g.lvl_sn = lvl_sn;
+    g.a_csr = a_csr;
+    g.a_off = a_off;
+    g.parent = parent;
+    g.rel = rel;
+    g.rel_off = rel_off;
+    g.ext = ext;
+    g.panel_sn = panel_sn;
+    g.upd = upd;
+    g.rows = c->d_rows;
+    g.status = ptr_at<int>(w, L, L_GF_STATUS);
+    c->d_Asnap = w + L.off[L_GF_ASNAP];
+    HIP_TRY(hipHostMalloc((void **)&c->h_gf_status, sizeof(int), hipHostMallocDefault));
+    *c->h_gf_status = 0;
+    HIP_TRY(hipStreamCreateWithFlags(&c->factor_stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_gf_done, hipEventDisableTiming));
+  }
   // backward levels are launched top-down: index L of the loop is level nl-1-L
   c->th = std::thread(factor_main, c);
   return FE_OK;
@@ -985,8 +1151,9 @@ int fe_factor_async(fe_ctx *c, const void *A_vals, int64_t tag, void *stream) {
 int fe_factor_status(fe_ctx *c, int64_t *ready_tag) {
   if (!c) return FE_EINVAL;
   std::lock_guard<std::mutex> lk(c->mu);
+  const bool busy = factor_busy_locked(c);
   if (ready_tag) *ready_tag = c->ready_tag;
-  if (c->job_pending || c->job_running) return FE_EBUSY;
+  if (busy) return FE_EBUSY;
   if (c->job_status != FE_OK) return c->fail(c->job_status, "%s", c->job_err.c_str());
   return FE_OK;
 }
@@ -1156,10 +1323,12 @@ int fe_reset(fe_ctx *c) {
   if (!c) return FE_EINVAL;
   std::unique_lock<std::mutex> lk(c->mu);
   c->cv.wait(lk, [&] { return !c->job_pending && !c->job_running; });
+  if (c->gpu_factor) (void)gf_collect_locked(c, true);
   c->step_count = 0;
   c->active_slot = -1;
   c->installed_tag = -1;
   c->ready_tag = -1;
+  c->ready_slot = -1;
   c->job_status = FE_OK;
   c->have_prev_a = false;
   return FE_OK;

@@ -80,6 +80,52 @@ constexpr int kBwdRowsMax = 1024;  // rows per backward tile: 64..1024 (option)
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
                     int32_t bwd_rows, Symbolic &S);
 
+// ------------------------------------------- GPU factorisation plan
+// One frontal matrix of the GPU multifrontal factorisation.  The front is
+// eliminated with an augmented block X (m x nc, row-major, starts as the
+// identity on the own rows): the row operations of the elimination turn it
+// into [L11^{-1}; -L21 L11^{-1}], i.e. the explicit-inverse panel.
+struct GfFront {
+  int32_t m, nc;       // front order and eliminated columns
+  int64_t offF;        // m x m column-major FP64 front (lower part used)
+  int64_t offX;        // m x nc row-major FP64 augmented block
+  int64_t offW;        // m x 32 column-major FP64 panel scratch
+  int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
+  int64_t panel_off;   // output panel offset, as Supernode::panel_off
+};
+struct GfTile {        // 64 x 64 tile of a trailing update
+  int32_t s, region, i0, j0;  // region 0: front F, region 1: augmented block X
+};
+struct GfExt {         // 32 x 32 tile of a child's update matrix (extend-add)
+  int32_t child, i0, j0, pad;
+};
+constexpr int kGfPanel = 32;   // panel width of the GPU factorisation
+constexpr int kGfTile = 64;    // trailing-update tile
+
+struct GfPlan {
+  std::vector<GfFront> fr;                   // by supernode
+  int64_t doubles = 0;                       // front storage (FP64 entries)
+  std::vector<int32_t> lvl_sn, lvl_ptr;      // supernodes of each level
+  std::vector<int64_t> lvl_lo, lvl_hi;       // storage range of each level
+  std::vector<int32_t> a_csr;                // A scatter: CSR slot ...
+  std::vector<int64_t> a_off, a_ptr;         // ... -> front entry; per-level ranges
+  std::vector<int32_t> parent;               // supernode -> parent (or -1)
+  std::vector<int32_t> rel;                  // child struct row -> parent front row
+  std::vector<int64_t> rel_off;              // by supernode, into rel
+  std::vector<GfExt> ext;                    // extend-add tiles, by parent level
+  std::vector<int64_t> ext_ptr;
+  std::vector<int32_t> step_k0;              // panel steps: k0 of each step
+  std::vector<int32_t> step_level;           // level of each step
+  std::vector<int32_t> panel_sn;             // fronts with nc > k0, per step
+  std::vector<int64_t> panel_ptr;
+  std::vector<GfTile> upd;                   // trailing-update tiles, per step
+  std::vector<int64_t> upd_ptr;
+  std::vector<int32_t> lvl_step_ptr;         // steps of each level
+  double flops = 0.0;
+};
+
+std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G);
+
 // ------------------------------------------------------- numeric factor
 // Parallel-for helper (dynamic scheduling on std::threads).
 void parallel_for(int64_t n, int n_threads, const std::function<void(int64_t, int)> &fn);

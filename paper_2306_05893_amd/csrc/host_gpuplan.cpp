@@ -1,0 +1,131 @@
+// Static plan of the GPU multifrontal factorisation: front storage, the A
+// scatter lists, the extend-add index maps and tiles, and the per-panel-step
+// tile lists of the trailing updates.  Built once per topology from the
+// supernodal structure (the same assembly tree as the host factorisation).
+#include <algorithm>
+
+#include "host.hpp"
+
+namespace fe {
+
+std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
+  G = GfPlan();
+  const int32_t ns = (int32_t)S.sn.size();
+  const int32_t nl = S.n_levels;
+  G.fr.resize(ns);
+  G.parent.resize(ns);
+  std::vector<std::vector<int32_t>> by_level(nl);
+  for (int32_t s = 0; s < ns; ++s) by_level[S.sn[s].level].push_back(s);
+
+  // front storage in level order, so that a level is one contiguous range
+  int64_t cur = 0;
+  G.lvl_ptr.assign(1, 0);
+  for (int32_t L = 0; L < nl; ++L) {
+    G.lvl_lo.push_back(cur);
+    for (int32_t s : by_level[L]) {
+      const Supernode &sn = S.sn[s];
+      GfFront &f = G.fr[s];
+      f.m = sn.m;
+      f.nc = sn.nc;
+      f.offF = cur;
+      cur += (int64_t)sn.m * sn.m;
+      f.offX = cur;
+      cur += (int64_t)sn.m * sn.nc;
+      f.offW = cur;
+      cur += (int64_t)sn.m * kGfPanel;
+      cur = (cur + 31) / 32 * 32;
+      f.rows_off = sn.rows_off;
+      f.panel_off = sn.panel_off;
+      G.lvl_sn.push_back(s);
+      G.parent[s] = sn.parent;
+    }
+    G.lvl_hi.push_back(cur);
+    G.lvl_ptr.push_back((int32_t)G.lvl_sn.size());
+  }
+  G.doubles = cur;
+
+  // front position of every panel row, per supernode (DOF -> row)
+  std::vector<int32_t> pos(P.n, -1);
+
+  // extend-add maps: child struct row ii -> position in the parent's front
+  G.rel_off.assign(ns + 1, 0);
+  for (int32_t s = 0; s < ns; ++s) {
+    G.rel_off[s] = (int64_t)G.rel.size();
+    const int32_t p = S.sn[s].parent;
+    if (p < 0) continue;
+    const Supernode &ps = S.sn[p];
+    const int32_t *prow = S.rows.data() + ps.rows_off;
+    for (int32_t i = 0; i < ps.m; ++i) pos[prow[i]] = i;
+    const Supernode &cs = S.sn[s];
+    const int32_t *crow = S.rows.data() + cs.rows_off;
+    for (int32_t ii = cs.nc; ii < cs.m; ++ii) {
+      const int32_t q = pos[crow[ii]];
+      if (q < 0) return "child row missing from the parent front";
+      G.rel.push_back(q);
+    }
+    for (int32_t i = 0; i < ps.m; ++i) pos[prow[i]] = -1;
+  }
+  G.rel_off[ns] = (int64_t)G.rel.size();
+
+  G.a_ptr.assign(1, 0);
+  G.ext_ptr.assign(1, 0);
+  G.lvl_step_ptr.assign(1, 0);
+  G.panel_ptr.assign(1, 0);
+  G.upd_ptr.assign(1, 0);
+  double flops = 0.0;
+  for (int32_t L = 0; L < nl; ++L) {
+    // A scatter: lower part of the own columns
+    for (int32_t s : by_level[L]) {
+      const Supernode &sn = S.sn[s];
+      const int32_t *rw = S.rows.data() + sn.rows_off;
+      for (int32_t i = 0; i < sn.m; ++i) pos[rw[i]] = i;
+      for (int32_t j = 0; j < sn.nc; ++j) {
+        const int32_t d = rw[j];
+        for (int32_t k = P.row_ptr[d]; k < P.row_ptr[d + 1]; ++k) {
+          const int32_t r = pos[P.col_idx[k]];
+          if (r >= j) {
+            G.a_csr.push_back(k);
+            G.a_off.push_back(G.fr[s].offF + (int64_t)j * sn.m + r);
+          }
+        }
+      }
+      for (int32_t i = 0; i < sn.m; ++i) pos[rw[i]] = -1;
+    }
+    G.a_ptr.push_back((int64_t)G.a_csr.size());
+    // extend-add tiles of the children of this level's fronts
+    for (int32_t s : by_level[L])
+      for (int32_t c : S.children[s]) {
+        const int32_t nr = S.sn[c].m - S.sn[c].nc;
+        for (int32_t j0 = 0; j0 < nr; j0 += 32)
+          for (int32_t i0 = j0; i0 < nr; i0 += 32) G.ext.push_back({c, i0, j0, 0});
+      }
+    G.ext_ptr.push_back((int64_t)G.ext.size());
+    // panel steps
+    int32_t maxnc = 0;
+    for (int32_t s : by_level[L]) maxnc = std::max(maxnc, S.sn[s].nc);
+    for (int32_t k0 = 0; k0 < maxnc; k0 += kGfPanel) {
+      G.step_k0.push_back(k0);
+      G.step_level.push_back(L);
+      for (int32_t s : by_level[L]) {
+        const Supernode &sn = S.sn[s];
+        if (sn.nc <= k0) continue;
+        G.panel_sn.push_back(s);
+        const int32_t k1 = std::min(k0 + kGfPanel, sn.nc);
+        const int32_t kb = k1 - k0;
+        for (int32_t j0 = k1; j0 < sn.m; j0 += kGfTile)
+          for (int32_t i0 = j0; i0 < sn.m; i0 += kGfTile) G.upd.push_back({s, 0, i0, j0});
+        for (int32_t i0 = k1; i0 < sn.m; i0 += kGfTile)
+          for (int32_t j0 = 0; j0 < k1; j0 += kGfTile) G.upd.push_back({s, 1, i0, j0});
+        const double t = sn.m - k1;
+        flops += 2.0 * kb * (t * t / 2.0 + t * k1);
+      }
+      G.panel_ptr.push_back((int64_t)G.panel_sn.size());
+      G.upd_ptr.push_back((int64_t)G.upd.size());
+    }
+    G.lvl_step_ptr.push_back((int32_t)G.step_k0.size());
+  }
+  G.flops = flops;
+  return "";
+}
+
+}  // namespace fe

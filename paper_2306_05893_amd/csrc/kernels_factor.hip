@@ -1,0 +1,346 @@
+// GPU multifrontal LDL^T factorisation in FP64 (the refactorisation of the
+// stale preconditioner, run on the device instead of a host thread).
+//
+// Per nested-dissection level (leaves first):
+//   init     zero the level's fronts; augmented block X = [I; 0]
+//   scatter  lower part of the own columns of A into the fronts
+//   extend   children's update matrices (the Schur complements left in the
+//            trailing part of their fronts) added into the parent fronts
+//   panels   for k0 = 0, 32, ...: one workgroup per front factors the
+//            32 x 32 diagonal block in LDS; one thread per row below solves
+//            that row against the block, and one thread per column of X
+//            applies the block's row operations to the panel rows of X
+//            (panel values in registers); then 64 x 64
+//            tiles update the trailing lower part of F and the rows of X
+//            below the panel (FP64 FMA tiles)
+//   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
+//            1/d into dinv
+// The row operations of the elimination applied to X = [I; 0] leave
+// X = [L11^{-1}; -L21 L11^{-1}], the explicit-inverse panel the triangular
+// sweeps use (the same numbers as the host factorisation).
+#include "device.hpp"
+#include "host.hpp"
+
+namespace fe {
+
+namespace {
+
+constexpr int NB = kGfPanel;
+constexpr int TL = kGfTile;
+
+__global__ void k_gf_zero(int64_t n, double *p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+// X = identity on the own rows (one block per front)
+__global__ void k_gf_xdiag(const GfFront *fr, const int32_t *sn, double *base) {
+  const GfFront f = fr[sn[blockIdx.x]];
+  for (int i = threadIdx.x; i < f.nc; i += blockDim.x) base[f.offX + (int64_t)i * f.nc + i] = 1.0;
+}
+
+template <typename TA>
+__global__ void k_gf_scatter(int64_t n, const int32_t *a_csr, const int64_t *a_off, const TA *A,
+                             double *base) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) base[a_off[i]] = (double)A[a_csr[i]];
+}
+
+// extend-add: one 32 x 32 tile of a child's update matrix per block
+__global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, const GfFront *fr,
+                                                   const int32_t *parent, const int32_t *rel,
+                                                   const int64_t *rel_off, double *base) {
+  const GfExt t = ext[blockIdx.x];
+  const GfFront fc = fr[t.child];
+  const GfFront fp = fr[parent[t.child]];
+  const int nr = fc.m - fc.nc;
+  const int32_t *rl = rel + rel_off[t.child];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int ii = t.i0 + tx;
+  if (ii >= nr) return;
+  const int pi = rl[ii];
+  for (int jj = t.j0 + ty; jj < min(t.j0 + 32, nr); jj += 8) {
+    if (ii < jj) continue;
+    const double u = base[fc.offF + (int64_t)(fc.nc + jj) * fc.m + fc.nc + ii];
+    const int pj = rl[jj];
+    const int64_t o = pi >= pj ? (int64_t)pj * fp.m + pi : (int64_t)pi * fp.m + pj;
+    atomicAdd(base + fp.offF + o, u);
+  }
+}
+
+// Diagonal block of the panel (columns [k0, k1)) of one front, one workgroup:
+// unblocked LDL^T of the kb x kb block in LDS (diagonal keeps d, below it L).
+__global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_t *sn, int k0,
+                                                 double *base, int *status) {
+  const GfFront f = fr[sn[blockIdx.x]];
+  const int m = f.m, nc = f.nc;
+  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
+  double *F = base + f.offF;
+  __shared__ double D[NB][NB + 1];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < kb * kb; idx += 256) {
+    const int r = idx % kb, c = idx / kb;
+    D[r][c] = r >= c ? F[(int64_t)(k0 + c) * m + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < kb; ++k) {
+    double d = D[k][k];
+    if (!(d > 0.0)) {
+      if (tid == 0) atomicOr(status, 1);
+      d = 1.0;  // keep going; the host discards this factor
+    }
+    const double inv = 1.0 / d;
+    const int w = kb - k - 1;
+    for (int idx = tid; idx < w * w; idx += 256) {
+      const int r = k + 1 + idx / w, c = k + 1 + idx % w;
+      if (c <= r) D[r][c] -= D[r][k] * D[c][k] * inv;
+    }
+    __syncthreads();
+    if (tid > k && tid < kb) D[tid][k] *= inv;
+    if (tid == 0) D[k][k] = d;
+    __syncthreads();
+  }
+  for (int idx = tid; idx < kb * kb; idx += 256) {
+    const int r = idx % kb, c = idx / kb;
+    if (r >= c) F[(int64_t)(k0 + c) * m + k0 + r] = D[r][c];
+  }
+}
+
+// Rows below the diagonal block (one thread per row, the kb panel values in
+// registers): with the factored block (unit L_d, pivots d), row i becomes
+//   f_k <- f_k - sum_{c<k} l_c L_d[k][c],  W[i, k] = f_k,  l_k = f_k / d_k.
+// blockIdx.y = front of the step, blockIdx.x = chunk of 256 rows.
+__global__ __launch_bounds__(256) void k_gf_rows(const GfFront *fr, const int32_t *sn, int k0,
+                                                 double *base) {
+  const GfFront f = fr[sn[blockIdx.y]];
+  const int m = f.m, nc = f.nc;
+  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
+  const int i = k1 + (int)(blockIdx.x * 256 + threadIdx.x);
+  if (k1 + (int)(blockIdx.x * 256) >= m) return;  // whole block past the front
+  double *F = base + f.offF;
+  double *W = base + f.offW;
+  __shared__ double D[NB][NB + 1];
+  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
+    const int r = idx % kb, c = idx / kb;
+    D[r][c] = r >= c ? F[(int64_t)(k0 + c) * m + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  if (i >= m) return;
+  double v[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) v[c] = c < kb ? F[(int64_t)(k0 + c) * m + i] : 0.0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k < kb) {
+      W[(int64_t)k * m + i] = v[k];
+      const double l = v[k] / D[k][k];
+#pragma unroll
+      for (int c = k + 1; c < NB; ++c)
+        if (c < kb) v[c] -= v[k] * D[c][k];
+      v[k] = l;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c)
+    if (c < kb) F[(int64_t)(k0 + c) * m + i] = v[c];
+}
+
+// Row operations of the panel on the panel rows of X: per column c < k1 of
+// X (one thread each, independent), forward substitution with the unit
+// lower factor of the diagonal block:
+//   x_r <- x_r - sum_{k<r} L_d[r][k] x_k   for the kb rows of the panel.
+// blockIdx.y = front of the step, blockIdx.x = chunk of 256 columns.
+__global__ __launch_bounds__(256) void k_gf_xpanel(const GfFront *fr, const int32_t *sn, int k0,
+                                                   double *base) {
+  const GfFront f = fr[sn[blockIdx.y]];
+  const int m = f.m, nc = f.nc;
+  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
+  const int c = (int)(blockIdx.x * 256 + threadIdx.x);
+  if ((int)(blockIdx.x * 256) >= k1) return;  // whole block past the columns
+  const double *F = base + f.offF;
+  double *X = base + f.offX;
+  __shared__ double D[NB][NB + 1];
+  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
+    const int r = idx % kb, cc = idx / kb;
+    D[r][cc] = r > cc ? F[(int64_t)(k0 + cc) * m + k0 + r] : 0.0;
+  }
+  __syncthreads();
+  if (c >= k1) return;
+  double x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) x[r] = r < kb ? X[(int64_t)(k0 + r) * nc + c] : 0.0;
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int r = k + 1; r < NB; ++r)
+      if (r < kb) x[r] -= D[r][k] * x[k];
+#pragma unroll
+  for (int r = 0; r < NB; ++r)
+    if (r < kb) X[(int64_t)(k0 + r) * nc + c] = x[r];
+}
+
+// Trailing update of one 64 x 64 tile:
+//   region 0: F[i, j] -= sum_k L[i, k0+k] W[j, k]        (i >= j >= k1)
+//   region 1: X[i, j] -= sum_k L[i, k0+k] X[k0+k, j]     (i >= k1, j < k1)
+__global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const GfFront *fr, int k0,
+                                                   double *base) {
+  const GfTile t = tiles[blockIdx.x];
+  const GfFront f = fr[t.s];
+  const int m = f.m, nc = f.nc;
+  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
+  double *F = base + f.offF;
+  double *X = base + f.offX;
+  const double *W = base + f.offW;
+  __shared__ double sA[NB][TL + 1];
+  __shared__ double sB[NB][TL + 1];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < NB * TL; idx += 256) {
+    const int k = idx / TL, r = idx % TL;
+    const int i = t.i0 + r;
+    sA[k][r] = (k < kb && i < m) ? F[(int64_t)(k0 + k) * m + i] : 0.0;
+    const int j = t.j0 + r;
+    double b = 0.0;
+    if (k < kb) {
+      if (t.region == 0) b = j < m ? W[(int64_t)k * m + j] : 0.0;
+      else b = j < k1 ? X[(int64_t)(k0 + k) * nc + j] : 0.0;
+    }
+    sB[k][r] = b;
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  if (t.region == 0) {
+    // consecutive threads -> consecutive rows (column-major F)
+    for (int k = 0; k < kb; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = sA[k][tx + 16 * u];
+        b[u] = sB[k][ty + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = t.j0 + ty + 16 * v;
+      if (j >= m) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = t.i0 + tx + 16 * u;
+        if (i < m && i >= j) F[(int64_t)j * m + i] -= acc[u][v];
+      }
+    }
+  } else {
+    // consecutive threads -> consecutive columns (row-major X)
+    for (int k = 0; k < kb; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = sA[k][ty + 16 * u];
+        b[u] = sB[k][tx + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = t.i0 + ty + 16 * u;
+      if (i >= m) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = t.j0 + tx + 16 * v;
+        if (j < k1) X[(int64_t)i * nc + j] -= acc[u][v];
+      }
+    }
+  }
+}
+
+// panel G (m x nc column-major) from X and 1/d; blockIdx.y = front of the level
+template <typename T>
+__global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_t *sn,
+                                                 const double *base, const int32_t *rows,
+                                                 T *panels, T *dinv) {
+  const GfFront f = fr[sn[blockIdx.y]];
+  const int64_t total = (int64_t)f.m * f.nc;
+  const double *X = base + f.offX;
+  T *G = panels + f.panel_off;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+    const int i = (int)(idx % f.m), j = (int)(idx / f.m);
+    const double x = X[(int64_t)i * f.nc + j];
+    G[idx] = (T)(i < f.nc ? x : -x);
+  }
+  if (blockIdx.x == 0) {
+    const int32_t *rw = rows + f.rows_off;
+    const double *F = base + f.offF;
+    for (int k = threadIdx.x; k < f.nc; k += blockDim.x)
+      dinv[rw[k]] = (T)(1.0 / F[(int64_t)k * f.m + k]);
+  }
+}
+
+}  // namespace
+
+template <typename TA, typename T>
+void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA *A, T *panels,
+                       T *dinv) {
+  const int nl = (int)P.lvl_lo.size();
+  for (int L = 0; L < nl; ++L) {
+    const int f0 = P.lvl_ptr[L], nf = P.lvl_ptr[L + 1] - f0;
+    if (nf == 0) continue;
+    const int64_t nz = P.lvl_hi[L] - P.lvl_lo[L];
+    const int64_t zb = std::min<int64_t>((nz + 255) / 256, 16384);
+    k_gf_zero<<<(unsigned)zb, 256, 0, st>>>(nz, d.fronts + P.lvl_lo[L]);
+    k_gf_xdiag<<<nf, 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts);
+    const int64_t a0 = P.a_ptr[L], na = P.a_ptr[L + 1] - a0;
+    if (na > 0)
+      k_gf_scatter<TA><<<(unsigned)((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0,
+                                                                      A, d.fronts);
+    const int64_t e0 = P.ext_ptr[L], ne = P.ext_ptr[L + 1] - e0;
+    if (ne > 0)
+      k_gf_extend<<<(unsigned)ne, 256, 0, st>>>(d.ext + e0, d.fr, d.parent, d.rel, d.rel_off,
+                                                d.fronts);
+    for (int s = P.lvl_step_ptr[L]; s < P.lvl_step_ptr[L + 1]; ++s) {
+      const int k0 = P.step_k0[s];
+      const int64_t p0 = P.panel_ptr[s], np = P.panel_ptr[s + 1] - p0;
+      if (np > 0) {
+        k_gf_diag<<<(unsigned)np, 256, 0, st>>>(d.fr, d.panel_sn + p0, k0, d.fronts, d.status);
+        int maxrows = 0;
+        for (int64_t q = p0; q < p0 + np; ++q) {
+          const GfFront &g = P.fr[P.panel_sn[q]];
+          maxrows = std::max(maxrows, g.m - std::min(k0 + NB, g.nc));
+        }
+        if (maxrows > 0)
+          k_gf_rows<<<dim3((unsigned)((maxrows + 255) / 256), (unsigned)np), 256, 0, st>>>(
+              d.fr, d.panel_sn + p0, k0, d.fronts);
+        const int k1max = k0 + NB;  // columns [0, k1) of X, k1 <= k0 + NB
+        k_gf_xpanel<<<dim3((unsigned)((k1max + 255) / 256), (unsigned)np), 256, 0, st>>>(
+            d.fr, d.panel_sn + p0, k0, d.fronts);
+      }
+      const int64_t u0 = P.upd_ptr[s], nu = P.upd_ptr[s + 1] - u0;
+      if (nu > 0) k_gf_update<<<(unsigned)nu, 256, 0, st>>>(d.upd + u0, d.fr, k0, d.fronts);
+    }
+    int64_t maxe = 0;
+    for (int k = f0; k < f0 + nf; ++k) {
+      const GfFront &g = P.fr[P.lvl_sn[k]];
+      maxe = std::max<int64_t>(maxe, (int64_t)g.m * g.nc);
+    }
+    const unsigned gx = (unsigned)std::min<int64_t>((maxe + 255) / 256, 1024);
+    k_gf_emit<T><<<dim3(gx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts, d.rows, panels, dinv);
+  }
+}
+
+template void launch_gpu_factor<float, float>(hipStream_t, const GfPlan &, const GfDev &,
+                                              const float *, float *, float *);
+template void launch_gpu_factor<double, double>(hipStream_t, const GfPlan &, const GfDev &,
+                                                const double *, double *, double *);
+
+}  // namespace fe

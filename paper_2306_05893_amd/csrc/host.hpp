@@ -93,14 +93,14 @@ struct GfFront {
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
   int64_t panel_off;   // output panel offset, as Supernode::panel_off
 };
-struct GfTile {        // 64 x 64 tile of a trailing update
+struct GfTile {        // kGfTile x kGfTile tile of a trailing update
   int32_t s, region, i0, j0;  // region 0: front F, region 1: augmented block X
 };
 struct GfExt {         // 32 x 32 tile of a child's update matrix (extend-add)
   int32_t child, i0, j0, pad;
 };
 constexpr int kGfPanel = 32;   // panel width of the GPU factorisation
-constexpr int kGfTile = 64;    // trailing-update tile
+constexpr int kGfTile = 128;   // trailing-update tile
 
 struct GfPlan {
   std::vector<GfFront> fr;                   // by supernode

@@ -12,7 +12,7 @@
 //            applies the block's row operations to the panel rows of X
 //            (panel values in registers); then 64 x 64
 //            tiles update the trailing lower part of F and the rows of X
-//            below the panel (FP64 FMA tiles)
+//            below the panel (FP64 FMA tiles, 128 x 128)
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave
@@ -146,8 +146,8 @@ __global__ __launch_bounds__(256) void k_gf_rows(const GfFront *fr, const int32_
 }
 
 // Row operations of the panel on the panel rows of X: per column c < k1 of
-// X (one thread each, independent), forward substitution with the unit
-// lower factor of the diagonal block:
+// X (one thread each, independent; values staged in LDS), forward
+// substitution with the unit lower factor of the diagonal block:
 //   x_r <- x_r - sum_{k<r} L_d[r][k] x_k   for the kb rows of the panel.
 // blockIdx.y = front of the step, blockIdx.x = chunk of 256 columns.
 __global__ __launch_bounds__(256) void k_gf_xpanel(const GfFront *fr, const int32_t *sn, int k0,
@@ -160,26 +160,23 @@ __global__ __launch_bounds__(256) void k_gf_xpanel(const GfFront *fr, const int3
   const double *F = base + f.offF;
   double *X = base + f.offX;
   __shared__ double D[NB][NB + 1];
+  __shared__ double sx[NB][256 + 1];  // column values of this block's columns
   for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
     const int r = idx % kb, cc = idx / kb;
     D[r][cc] = r > cc ? F[(int64_t)(k0 + cc) * m + k0 + r] : 0.0;
   }
+  const bool active = c < k1;
+  for (int r = 0; r < kb; ++r) sx[r][threadIdx.x] = active ? X[(int64_t)(k0 + r) * nc + c] : 0.0;
   __syncthreads();
-  if (c >= k1) return;
-  double x[NB];
-#pragma unroll
-  for (int r = 0; r < NB; ++r) x[r] = r < kb ? X[(int64_t)(k0 + r) * nc + c] : 0.0;
-#pragma unroll
-  for (int k = 0; k < NB; ++k)
-#pragma unroll
-    for (int r = k + 1; r < NB; ++r)
-      if (r < kb) x[r] -= D[r][k] * x[k];
-#pragma unroll
-  for (int r = 0; r < NB; ++r)
-    if (r < kb) X[(int64_t)(k0 + r) * nc + c] = x[r];
+  for (int k = 0; k < kb; ++k) {
+    const double xk = sx[k][threadIdx.x];
+    for (int r = k + 1; r < kb; ++r) sx[r][threadIdx.x] -= D[r][k] * xk;
+  }
+  if (active)
+    for (int r = 0; r < kb; ++r) X[(int64_t)(k0 + r) * nc + c] = sx[r][threadIdx.x];
 }
 
-// Trailing update of one 64 x 64 tile:
+// Trailing update of one 128 x 128 tile (8 x 8 outputs per thread):
 //   region 0: F[i, j] -= sum_k L[i, k0+k] W[j, k]        (i >= j >= k1)
 //   region 1: X[i, j] -= sum_k L[i, k0+k] X[k0+k, j]     (i >= k1, j < k1)
 __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const GfFront *fr, int k0,
@@ -191,8 +188,8 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   double *F = base + f.offF;
   double *X = base + f.offX;
   const double *W = base + f.offW;
-  __shared__ double sA[NB][TL + 1];
-  __shared__ double sB[NB][TL + 1];
+  __shared__ double sA[NB][TL + 2];
+  __shared__ double sB[NB][TL + 2];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < NB * TL; idx += 256) {
     const int k = idx / TL, r = idx % TL;
@@ -208,56 +205,47 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   }
   __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  constexpr int R = TL / 16;
+  double acc[R][R];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < R; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  if (t.region == 0) {
-    // consecutive threads -> consecutive rows (column-major F)
-    for (int k = 0; k < kb; ++k) {
-      double a[4], b[4];
+    for (int v = 0; v < R; ++v) acc[u][v] = 0.0;
+  // region 0: thread rows tx + 16u (consecutive threads -> consecutive rows of
+  // the column-major F); region 1: thread rows ty + 16u, columns tx + 16v
+  // (consecutive threads -> consecutive columns of the row-major X)
+  const int ra = t.region == 0 ? tx : ty, cb = t.region == 0 ? ty : tx;
+  for (int k = 0; k < kb; ++k) {
+    double a[R], bb[R];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = sA[k][tx + 16 * u];
-        b[u] = sB[k][ty + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    for (int u = 0; u < R; ++u) {
+      a[u] = sA[k][ra + 16 * u];
+      bb[u] = sB[k][cb + 16 * u];
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = t.j0 + ty + 16 * v;
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u][v] += a[u] * bb[v];
+  }
+  if (t.region == 0) {
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int j = t.j0 + cb + 16 * v;
       if (j >= m) continue;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = t.i0 + tx + 16 * u;
+      for (int u = 0; u < R; ++u) {
+        const int i = t.i0 + ra + 16 * u;
         if (i < m && i >= j) F[(int64_t)j * m + i] -= acc[u][v];
       }
     }
   } else {
-    // consecutive threads -> consecutive columns (row-major X)
-    for (int k = 0; k < kb; ++k) {
-      double a[4], b[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = sA[k][ty + 16 * u];
-        b[u] = sB[k][tx + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = t.i0 + ty + 16 * u;
+    for (int u = 0; u < R; ++u) {
+      const int i = t.i0 + ra + 16 * u;
       if (i >= m) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = t.j0 + tx + 16 * v;
+      for (int v = 0; v < R; ++v) {
+        const int j = t.j0 + cb + 16 * v;
         if (j < k1) X[(int64_t)i * nc + j] -= acc[u][v];
       }
     }

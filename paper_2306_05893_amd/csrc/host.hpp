@@ -89,7 +89,7 @@ struct GfFront {
   int32_t m, nc;       // front order and eliminated columns
   int64_t offF;        // m x m column-major FP64 front (lower part used)
   int64_t offX;        // m x nc row-major FP64 augmented block
-  int64_t offW;        // m x 32 column-major FP64 panel scratch
+  int64_t offW;        // m x kGfPanel column-major FP64 panel scratch
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
   int64_t panel_off;   // output panel offset, as Supernode::panel_off
 };
@@ -99,7 +99,7 @@ struct GfTile {        // kGfTile x kGfTile tile of a trailing update
 struct GfExt {         // 32 x 32 tile of a child's update matrix (extend-add)
   int32_t child, i0, j0, pad;
 };
-constexpr int kGfPanel = 32;   // panel width of the GPU factorisation
+constexpr int kGfPanel = 64;   // panel width of the GPU factorisation
 constexpr int kGfTile = 128;   // trailing-update tile
 
 struct GfPlan {

@@ -6,13 +6,12 @@
 //   scatter  lower part of the own columns of A into the fronts
 //   extend   children's update matrices (the Schur complements left in the
 //            trailing part of their fronts) added into the parent fronts
-//   panels   for k0 = 0, 32, ...: one workgroup per front factors the
-//            32 x 32 diagonal block in LDS; one thread per row below solves
-//            that row against the block, and one thread per column of X
-//            applies the block's row operations to the panel rows of X
-//            (panel values in registers); then 64 x 64
-//            tiles update the trailing lower part of F and the rows of X
-//            below the panel (FP64 FMA tiles, 128 x 128)
+//   panels   for k0 = 0, 64, ...: one workgroup per front factors the
+//            64 x 64 diagonal block in LDS; then one launch applies the
+//            block to the rows below it (one thread per row, panel values
+//            in registers) and its row operations to the panel rows of X
+//            (one thread per column); then 128 x 128 FP64 FMA tiles update
+//            the trailing lower part of F and the rows of X below the panel
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave
@@ -106,81 +105,90 @@ __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_
   }
 }
 
-// Rows below the diagonal block (one thread per row, the kb panel values in
-// registers): with the factored block (unit L_d, pivots d), row i becomes
-//   f_k <- f_k - sum_{c<k} l_c L_d[k][c],  W[i, k] = f_k,  l_k = f_k / d_k.
-// blockIdx.y = front of the step, blockIdx.x = chunk of 256 rows.
-__global__ __launch_bounds__(256) void k_gf_rows(const GfFront *fr, const int32_t *sn, int k0,
-                                                 double *base) {
+// Row operations of one panel step (one launch, two roles; the kb x kb
+// diagonal block, already factored, staged in LDS):
+//  * blockIdx.x < nrb: rows below the block, one thread per row with the kb
+//    panel values in registers:
+//      f_k <- f_k - sum_{c<k} l_c L_d[k][c],  W[i, k] = f_k,  l_k = f_k / d_k;
+//  * otherwise: columns c < k1 of the panel rows of X, one thread per
+//    column, forward substitution with the unit lower factor of the block:
+//      x_r <- x_r - sum_{k<r} L_d[r][k] x_k.
+// blockIdx.y = front of the step; chunks of 256 rows / 256 columns.
+__global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int32_t *sn, int k0,
+                                                   int nrb, double *base) {
   const GfFront f = fr[sn[blockIdx.y]];
   const int m = f.m, nc = f.nc;
   const int k1 = min(k0 + NB, nc), kb = k1 - k0;
-  const int i = k1 + (int)(blockIdx.x * 256 + threadIdx.x);
-  if (k1 + (int)(blockIdx.x * 256) >= m) return;  // whole block past the front
+  const bool rows_role = (int)blockIdx.x < nrb;
+  const int first = rows_role ? k1 + (int)blockIdx.x * 256 : ((int)blockIdx.x - nrb) * 256;
+  if (first >= (rows_role ? m : k1)) return;  // whole block past this front's work
   double *F = base + f.offF;
-  double *W = base + f.offW;
-  __shared__ double D[NB][NB + 1];
-  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
-    const int r = idx % kb, c = idx / kb;
-    D[r][c] = r >= c ? F[(int64_t)(k0 + c) * m + k0 + r] : 0.0;
+  // the block, transposed (Lt[k][c] = L_d[c][k], column k of L_d contiguous)
+  // and padded to NB x NB with the identity, so that the unrolled loops
+  // below need no bounds tests
+  __shared__ double Lt[NB][NB + 2];
+  __shared__ double dinv[NB];
+  for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
+    const int c = idx % NB, k = idx / NB;
+    double x = c == k ? 1.0 : 0.0;
+    if (c >= k && c < kb) x = F[(int64_t)(k0 + k) * m + k0 + c];
+    Lt[k][c] = x;
   }
   __syncthreads();
-  if (i >= m) return;
+  if (threadIdx.x < NB) dinv[threadIdx.x] = 1.0 / Lt[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  // Branch-free: loads clamped to the block's columns, and the stores of
+  // the padding columns c >= kb (last panel of a front) sent to the unused
+  // columns of the W scratch (m x NB; rows-role threads use rows >= k1 of
+  // it and X-role threads rows < k1, so the two never meet).
+  const uint32_t i = (uint32_t)(first + (int)threadIdx.x);
+  double *W = base + f.offW;
   double v[NB];
+  if (rows_role) {
+    if (i >= (uint32_t)m) return;
+    double *Fk = F + (int64_t)k0 * m;
 #pragma unroll
-  for (int c = 0; c < NB; ++c) v[c] = c < kb ? F[(int64_t)(k0 + c) * m + i] : 0.0;
+    for (int c = 0; c < NB; ++c) {
+      const double x = (Fk + (int64_t)min(c, kb - 1) * m)[i];
+      v[c] = c < kb ? x : 0.0;
+    }
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k < kb) {
-      W[(int64_t)k * m + i] = v[k];
-      const double l = v[k] / D[k][k];
+    for (int k = 0; k < NB; ++k) {
+      (W + (int64_t)k * m)[i] = v[k];
 #pragma unroll
-      for (int c = k + 1; c < NB; ++c)
-        if (c < kb) v[c] -= v[k] * D[c][k];
-      v[k] = l;
+      for (int c = k + 1; c < NB; ++c) v[c] -= v[k] * Lt[k][c];
+      v[k] *= dinv[k];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) ((c < kb ? Fk : W) + (int64_t)c * m)[i] = v[c];
+  } else {
+    if (i >= (uint32_t)k1) return;
+    double *Xk = base + f.offX + (int64_t)k0 * nc;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const double x = (Xk + (int64_t)min(r, kb - 1) * nc)[i];
+      v[r] = r < kb ? x : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+#pragma unroll
+      for (int r = k + 1; r < NB; ++r) v[r] -= Lt[k][r] * v[k];
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      double *dst = r < kb ? Xk + (int64_t)r * nc : W + (int64_t)r * m;
+      dst[i] = v[r];
     }
   }
-#pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < kb) F[(int64_t)(k0 + c) * m + i] = v[c];
 }
 
-// Row operations of the panel on the panel rows of X: per column c < k1 of
-// X (one thread each, independent; values staged in LDS), forward
-// substitution with the unit lower factor of the diagonal block:
-//   x_r <- x_r - sum_{k<r} L_d[r][k] x_k   for the kb rows of the panel.
-// blockIdx.y = front of the step, blockIdx.x = chunk of 256 columns.
-__global__ __launch_bounds__(256) void k_gf_xpanel(const GfFront *fr, const int32_t *sn, int k0,
-                                                   double *base) {
-  const GfFront f = fr[sn[blockIdx.y]];
-  const int m = f.m, nc = f.nc;
-  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
-  const int c = (int)(blockIdx.x * 256 + threadIdx.x);
-  if ((int)(blockIdx.x * 256) >= k1) return;  // whole block past the columns
-  const double *F = base + f.offF;
-  double *X = base + f.offX;
-  __shared__ double D[NB][NB + 1];
-  __shared__ double sx[NB][256 + 1];  // column values of this block's columns
-  for (int idx = threadIdx.x; idx < kb * kb; idx += 256) {
-    const int r = idx % kb, cc = idx / kb;
-    D[r][cc] = r > cc ? F[(int64_t)(k0 + cc) * m + k0 + r] : 0.0;
-  }
-  const bool active = c < k1;
-  for (int r = 0; r < kb; ++r) sx[r][threadIdx.x] = active ? X[(int64_t)(k0 + r) * nc + c] : 0.0;
-  __syncthreads();
-  for (int k = 0; k < kb; ++k) {
-    const double xk = sx[k][threadIdx.x];
-    for (int r = k + 1; r < kb; ++r) sx[r][threadIdx.x] -= D[r][k] * xk;
-  }
-  if (active)
-    for (int r = 0; r < kb; ++r) X[(int64_t)(k0 + r) * nc + c] = sx[r][threadIdx.x];
-}
-
-// Trailing update of one 128 x 128 tile (8 x 8 outputs per thread):
+// Trailing update of one 128 x 128 tile (8 x 8 outputs per thread, the
+// outputs loaded into the accumulators before the panel is staged):
 //   region 0: F[i, j] -= sum_k L[i, k0+k] W[j, k]        (i >= j >= k1)
 //   region 1: X[i, j] -= sum_k L[i, k0+k] X[k0+k, j]     (i >= k1, j < k1)
+// The panel's k range is staged through LDS 32 columns at a time.
 __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const GfFront *fr, int k0,
                                                    double *base) {
+  constexpr int KC = 32;
   const GfTile t = tiles[blockIdx.x];
   const GfFront f = fr[t.s];
   const int m = f.m, nc = f.nc;
@@ -188,46 +196,63 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   double *F = base + f.offF;
   double *X = base + f.offX;
   const double *W = base + f.offW;
-  __shared__ double sA[NB][TL + 2];
-  __shared__ double sB[NB][TL + 2];
+  __shared__ double sA[KC][TL + 2];
+  __shared__ double sB[KC][TL + 2];
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < NB * TL; idx += 256) {
-    const int k = idx / TL, r = idx % TL;
-    const int i = t.i0 + r;
-    sA[k][r] = (k < kb && i < m) ? F[(int64_t)(k0 + k) * m + i] : 0.0;
-    const int j = t.j0 + r;
-    double b = 0.0;
-    if (k < kb) {
-      if (t.region == 0) b = j < m ? W[(int64_t)k * m + j] : 0.0;
-      else b = j < k1 ? X[(int64_t)(k0 + k) * nc + j] : 0.0;
-    }
-    sB[k][r] = b;
-  }
-  __syncthreads();
   const int tx = tid & 15, ty = tid >> 4;
   constexpr int R = TL / 16;
-  double acc[R][R];
-#pragma unroll
-  for (int u = 0; u < R; ++u)
-#pragma unroll
-    for (int v = 0; v < R; ++v) acc[u][v] = 0.0;
   // region 0: thread rows tx + 16u (consecutive threads -> consecutive rows of
   // the column-major F); region 1: thread rows ty + 16u, columns tx + 16v
   // (consecutive threads -> consecutive columns of the row-major X)
-  const int ra = t.region == 0 ? tx : ty, cb = t.region == 0 ? ty : tx;
-  for (int k = 0; k < kb; ++k) {
-    double a[R], bb[R];
+  const bool r0 = t.region == 0;
+  const int ra = r0 ? tx : ty, cb = r0 ? ty : tx;
+  double acc[R][R];
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      a[u] = sA[k][ra + 16 * u];
-      bb[u] = sB[k][cb + 16 * u];
+  for (int u = 0; u < R; ++u) {
+    const int i = t.i0 + ra + 16 * u;
+#pragma unroll
+    for (int v = 0; v < R; ++v) {
+      const int j = t.j0 + cb + 16 * v;
+      double x = 0.0;
+      if (r0) {
+        if (i < m && j < m) x = F[(int64_t)j * m + i];
+      } else {
+        if (i < m && j < k1) x = X[(int64_t)i * nc + j];
+      }
+      acc[u][v] = x;
     }
-#pragma unroll
-    for (int u = 0; u < R; ++u)
-#pragma unroll
-      for (int v = 0; v < R; ++v) acc[u][v] += a[u] * bb[v];
   }
-  if (t.region == 0) {
+  for (int kc0 = 0; kc0 < kb; kc0 += KC) {
+    const int kn = min(KC, kb - kc0);
+    if (kc0 > 0) __syncthreads();
+    for (int idx = tid; idx < KC * TL; idx += 256) {
+      const int k = idx / TL, r = idx % TL;
+      const int kk = kc0 + k;
+      const int i = t.i0 + r;
+      sA[k][r] = (k < kn && i < m) ? F[(int64_t)(k0 + kk) * m + i] : 0.0;
+      const int j = t.j0 + r;
+      double b = 0.0;
+      if (k < kn) {
+        if (r0) b = j < m ? W[(int64_t)kk * m + j] : 0.0;
+        else b = j < k1 ? X[(int64_t)(k0 + kk) * nc + j] : 0.0;
+      }
+      sB[k][r] = b;
+    }
+    __syncthreads();
+    for (int k = 0; k < kn; ++k) {
+      double a[R], bb[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        a[u] = sA[k][ra + 16 * u];
+        bb[u] = sB[k][cb + 16 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < R; ++v) acc[u][v] = fma(-a[u], bb[v], acc[u][v]);
+    }
+  }
+  if (r0) {
 #pragma unroll
     for (int v = 0; v < R; ++v) {
       const int j = t.j0 + cb + 16 * v;
@@ -235,7 +260,7 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
 #pragma unroll
       for (int u = 0; u < R; ++u) {
         const int i = t.i0 + ra + 16 * u;
-        if (i < m && i >= j) F[(int64_t)j * m + i] -= acc[u][v];
+        if (i < m && i >= j) F[(int64_t)j * m + i] = acc[u][v];
       }
     }
   } else {
@@ -246,7 +271,7 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
 #pragma unroll
       for (int v = 0; v < R; ++v) {
         const int j = t.j0 + cb + 16 * v;
-        if (j < k1) X[(int64_t)i * nc + j] -= acc[u][v];
+        if (j < k1) X[(int64_t)i * nc + j] = acc[u][v];
       }
     }
   }
@@ -306,12 +331,10 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
           const GfFront &g = P.fr[P.panel_sn[q]];
           maxrows = std::max(maxrows, g.m - std::min(k0 + NB, g.nc));
         }
-        if (maxrows > 0)
-          k_gf_rows<<<dim3((unsigned)((maxrows + 255) / 256), (unsigned)np), 256, 0, st>>>(
-              d.fr, d.panel_sn + p0, k0, d.fronts);
-        const int k1max = k0 + NB;  // columns [0, k1) of X, k1 <= k0 + NB
-        k_gf_xpanel<<<dim3((unsigned)((k1max + 255) / 256), (unsigned)np), 256, 0, st>>>(
-            d.fr, d.panel_sn + p0, k0, d.fronts);
+        const int nrb = (maxrows + 255) / 256;
+        const int ncb = (k0 + NB + 255) / 256;  // columns [0, k1) of X, k1 <= k0 + NB
+        k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)np), 256, 0, st>>>(
+            d.fr, d.panel_sn + p0, k0, nrb, d.fronts);
       }
       const int64_t u0 = P.upd_ptr[s], nu = P.upd_ptr[s + 1] - u0;
       if (nu > 0) k_gf_update<<<(unsigned)nu, 256, 0, st>>>(d.upd + u0, d.fr, k0, d.fronts);

@@ -71,9 +71,11 @@ struct Symbolic {
 
 // Tile extents shared with the device kernels.
 constexpr int kFwdRows = 256;      // rows per forward tile (one per thread)
-constexpr int kFwdColsMax = 128;   // columns per forward tile: 8..128 (option)
 constexpr int kBwdCols = 16;       // columns per backward tile (4 per wavefront)
-constexpr int kBwdRowsMax = 1024;  // rows per backward tile: 64..1024 (option)
+// columns per forward tile: 16, 32, 64 or 128; rows per backward tile: 256,
+// 512 or 1024 (compile-time extents of the sweep kernels)
+inline bool valid_fwd_cols(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
+inline bool valid_bwd_rows(int r) { return r == 256 || r == 512 || r == 1024; }
 
 // Geometric nested dissection on the node graph, supernodes = ND blocks,
 // relaxed (dense) supernodal structure from the assembly tree.

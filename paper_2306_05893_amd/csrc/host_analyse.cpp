@@ -152,8 +152,8 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
   if (leaf_nodes <= 0) leaf_nodes = 48;
   if (fwd_cols <= 0) fwd_cols = 64;
   if (bwd_rows <= 0) bwd_rows = 512;
-  if (fwd_cols < 8 || fwd_cols > kFwdColsMax || bwd_rows < 64 || bwd_rows > kBwdRowsMax)
-    return "tile extents out of range";
+  if (!valid_fwd_cols(fwd_cols) || !valid_bwd_rows(bwd_rows))
+    return "tile extents: forward width 16, 32, 64 or 128; backward height 256, 512 or 1024";
   const int32_t N = P.n_nodes;
   S = Symbolic();
   S.n = P.n;

@@ -258,103 +258,130 @@ __global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
   z[i] = fixed[i] ? ri : 0.0;
 }
 
-constexpr int kFR = 256, kFCmax = 128;   // forward tile: 256 rows x (8..128) columns
-constexpr int kBC = 16, kBRmax = 1024;   // backward tile: 16 columns x (64..1024) rows
+constexpr int kFR = 256;  // forward tile: 256 rows x TC columns (TC: 16..128)
+constexpr int kBC = 16;   // backward tile: 16 columns x BR rows (BR: 256..1024)
 
 // Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
 // rows (one row per thread, consecutive rows = consecutive addresses of the
 // column-major panel); own rows (i < nc) accumulate into y, struct rows
 // subtract from w.  Entries above the diagonal of L11^{-1} are skipped.
-template <typename T>
+// All TC panel loads of a row are issued before the gather of the inputs
+// w[rows[j]] (an index load and a dependent load), so one tile costs about
+// three memory latencies instead of one per group of columns.
+template <typename T, int TC>
 __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
                                                  const SnDev *__restrict__ sn,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels, T *w, T *y,
-                                                 const PcgState *s, int TC) {
+                                                 const PcgState *s) {
   if (s && s->done) return;
-  __shared__ T s_in[kFCmax];
+  __shared__ T s_in[TC];
   const TileDev t = tiles[blockIdx.x];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
-  const int c0 = t.c0, c1 = min(d.nc, c0 + TC);
-  if ((int)threadIdx.x < c1 - c0) s_in[threadIdx.x] = w[rw[c0 + threadIdx.x]];
-  __syncthreads();
-  const int i = t.r0 + (int)threadIdx.x;
-  if (i >= d.m) return;
-  const int cnt = ((i < d.nc) ? min(c1, i + 1) : c1) - c0;
-  if (cnt <= 0) return;
+  const int c0 = t.c0, ncol = min(d.nc - c0, TC);
+  const int tid = (int)threadIdx.x;
+  const int i = t.r0 + tid;
+  const bool valid = i < d.m;
+  // index loads first, unconditional (clamped), so that no wait separates
+  // them from the panel loads issued next
+  const int32_t din = rw[c0 + min(tid, ncol - 1)];
+  const int32_t dout = rw[min(i, d.m - 1)];
+  // columns of this row inside the tile (own rows stop at the diagonal)
+  const int lim = !valid ? 0 : (i < d.nc ? min(ncol, i + 1 - c0) : ncol);
   const int64_t m = d.m;
-  const T *G = panels + d.panel_off + (int64_t)c0 * m + i;
-  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
-  int j = 0;
-  for (; j + 8 <= cnt; j += 8) {
-    const T g0 = G[0], g1 = G[m], g2 = G[2 * m], g3 = G[3 * m];
-    const T g4 = G[4 * m], g5 = G[5 * m], g6 = G[6 * m], g7 = G[7 * m];
-    a0 += g0 * s_in[j] + g4 * s_in[j + 4];
-    a1 += g1 * s_in[j + 1] + g5 * s_in[j + 5];
-    a2 += g2 * s_in[j + 2] + g6 * s_in[j + 6];
-    a3 += g3 * s_in[j + 3] + g7 * s_in[j + 7];
-    G += 8 * m;
+  const T *G = panels + d.panel_off + (int64_t)c0 * m + (valid ? i : 0);
+  const bool full = ncol == TC && t.r0 + kFR <= d.m && (t.r0 >= d.nc || t.r0 + 1 >= c0 + TC);
+  T g[TC];
+  if (full) {
+#pragma unroll
+    for (int j = 0; j < TC; ++j) g[j] = G[j * m];
+  } else {
+#pragma unroll
+    for (int j = 0; j < TC; ++j) g[j] = j < lim ? G[j * m] : T(0);
   }
-  for (; j < cnt; ++j) {
-    a0 += G[0] * s_in[j];
-    G += m;
+  if (tid < TC) s_in[tid] = tid < ncol ? w[din] : T(0);
+  __syncthreads();
+  if (lim <= 0) return;
+  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll
+  for (int j = 0; j < TC; j += 4) {
+    a0 += g[j] * s_in[j];
+    a1 += g[j + 1] * s_in[j + 1];
+    a2 += g[j + 2] * s_in[j + 2];
+    a3 += g[j + 3] * s_in[j + 3];
   }
   const T acc = (a0 + a1) + (a2 + a3);
-  if (i < d.nc) atomicAdd(y + rw[i], acc);
-  else atomicAdd(w + rw[i], -acc);
+  if (i < d.nc) atomicAdd(y + dout, acc);
+  else atomicAdd(w + dout, -acc);
 }
 
 // Backward tile: x[rows[j]] += sum_{i in tile rows} G[i, j] v_i with
 // v_i = dinv y (own rows) or -x[rows[i]] (struct rows, already final).
-// Each wavefront handles 4 consecutive columns, loading the 4 column
-// segments together (lanes stride over rows); rows above a column's diagonal
-// hold explicit zeros in the panel, so no masking is needed past max(r0, j0).
-template <typename T>
+// Each wavefront handles 4 consecutive columns (lanes stride over rows) and
+// issues all BR/64 x 4 of its panel loads before the inputs v are gathered.
+// Rows above a column's diagonal (zeros of L11^{-1}) are not read.
+template <typename T, int BR>
 __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
                                                  const SnDev *__restrict__ sn,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels,
                                                  const T *__restrict__ dinv,
                                                  const T *__restrict__ y, double *z,
-                                                 const PcgState *s, int BR) {
+                                                 const PcgState *s) {
   if (s && s->done) return;
-  __shared__ T s_v[kBRmax];
+  constexpr int NI = BR / 64;
+  __shared__ T s_v[BR];
   const TileDev t = tiles[blockIdx.x];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
   const int r0 = t.r0, r1 = min(d.m, r0 + BR);
-  for (int k = threadIdx.x; k < r1 - r0; k += 256) {
-    const int i = r0 + k;
-    const int32_t dof = rw[i];
-    s_v[k] = (i < d.nc) ? dinv[dof] * y[dof] : (T)(-z[dof]);
-  }
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j0 = t.c0 + 4 * wv;
-  if (j0 >= d.nc) return;
-  const int nj = min(4, d.nc - j0);
+  const int nj = max(0, min(4, d.nc - j0));
   const int ibeg = max(r0, j0);
-  if (ibeg >= r1) return;
   const int64_t m = d.m;
-  const T *G = panels + d.panel_off + (int64_t)j0 * m;
-  T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
-  if (nj == 4) {
-    for (int i = ibeg + lane; i < r1; i += 64) {
-      const T v = s_v[i - r0];
-      const T g0 = G[i], g1 = G[m + i], g2 = G[2 * m + i], g3 = G[3 * m + i];
-      p0 += g0 * v;
-      p1 += g1 * v;
-      p2 += g2 * v;
-      p3 += g3 * v;
+  const T *G = panels + d.panel_off + (int64_t)min(j0, d.nc - 1) * m;
+  // index loads of the inputs first (clamped, unconditional), then the panel
+  // loads, then the input values
+  constexpr int NV = BR / 256;
+  int32_t dof[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) dof[u] = rw[min(r0 + (int)threadIdx.x + 256 * u, r1 - 1)];
+  T g[NI][4];
+  if (nj == 4 && ibeg == r0 && r1 == r0 + BR) {
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int i = r0 + lane + 64 * q;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) g[q][c] = G[c * m + i];
     }
   } else {
-    for (int i = ibeg + lane; i < r1; i += 64) {
-      const T v = s_v[i - r0];
-      p0 += G[i] * v;
-      if (nj > 1) p1 += G[m + i] * v;
-      if (nj > 2) p2 += G[2 * m + i] * v;
+#pragma unroll
+    for (int q = 0; q < NI; ++q) {
+      const int i = r0 + lane + 64 * q;
+      const bool ok = i >= ibeg && i < r1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) g[q][c] = (ok && c < nj) ? G[c * m + i] : T(0);
     }
+  }
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int k = (int)threadIdx.x + 256 * u, i = r0 + k;
+    const T own = dinv[dof[u]] * y[dof[u]];
+    const T st = (T)(-z[dof[u]]);
+    s_v[k] = i < r1 ? (i < d.nc ? own : st) : T(0);
+  }
+  __syncthreads();
+  if (nj == 0 || ibeg >= r1) return;
+  T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
+#pragma unroll
+  for (int q = 0; q < NI; ++q) {
+    const T v = s_v[lane + 64 * q];
+    p0 += g[q][0] * v;
+    p1 += g[q][1] * v;
+    p2 += g[q][2] * v;
+    p3 += g[q][3] * v;
   }
   const double q0 = wave_sum((double)p0), q1 = wave_sum((double)p1);
   const double q2 = wave_sum((double)p2), q3 = wave_sum((double)p3);
@@ -459,15 +486,32 @@ template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
                     int tile_cols) {
-  if (n_tiles > 0)
-    k_tri_fwd<T><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state, tile_cols);
+  if (n_tiles <= 0) return;
+  switch (tile_cols) {
+    case 16: k_tri_fwd<T, 16><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
+    case 32: k_tri_fwd<T, 32><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
+    case 64: k_tri_fwd<T, 64><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
+    case 128: k_tri_fwd<T, 128><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
+    default: throw std::runtime_error("forward tile width must be 16, 32, 64 or 128");
+  }
 }
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
                     const PcgState *state, int tile_rows) {
-  if (n_tiles > 0)
-    k_tri_bwd<T><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state, tile_rows);
+  if (n_tiles <= 0) return;
+  switch (tile_rows) {
+    case 256:
+      k_tri_bwd<T, 256><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      break;
+    case 512:
+      k_tri_bwd<T, 512><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      break;
+    case 1024:
+      k_tri_bwd<T, 1024><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      break;
+    default: throw std::runtime_error("backward tile height must be 256, 512 or 1024");
+  }
 }
 
 #define FE_INST(T)                                                                             \

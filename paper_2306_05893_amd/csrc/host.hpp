@@ -95,8 +95,15 @@ struct GfFront {
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
   int64_t panel_off;   // output panel offset, as Supernode::panel_off
 };
-struct GfTile {        // kGfTile x kGfTile tile of a trailing update
-  int32_t s, region, i0, j0;  // region 0: front F, region 1: augmented block X
+// kGfTile x kGfTile output tile of an update (L: the front's scaled lower
+// factor, d: its pivots, W = L D for the current panel, X: augmented block):
+//   region 0  F[i, j] -= sum_{k in panel} L[i, k] W[j, k]   k1 <= j < nc, i >= j
+//   region 1  X[i, j] -= sum_{k in panel} L[i, k] X[k, j]   k1 <= i < nc, j < k1
+//   region 2  F[i, j] -= sum_{k < nc} L[i, k] d_k L[j, k]   nc <= j <= i (Schur)
+//   region 3  X[i, j] -= sum_{k < nc} L[i, k] X[k, j]       i >= nc, j < nc
+// Regions 0/1 run after each panel step; 2/3 once the own columns are done.
+struct GfTile {
+  int32_t s, region, i0, j0;
 };
 struct GfExt {         // 32 x 32 tile of a child's update matrix (extend-add)
   int32_t child, i0, j0, pad;
@@ -120,8 +127,9 @@ struct GfPlan {
   std::vector<int32_t> step_level;           // level of each step
   std::vector<int32_t> panel_sn;             // fronts with nc > k0, per step
   std::vector<int64_t> panel_ptr;
-  std::vector<GfTile> upd;                   // trailing-update tiles, per step
-  std::vector<int64_t> upd_ptr;
+  std::vector<GfTile> upd;                   // update tiles (regions 0-3)
+  std::vector<int64_t> upd_lo, upd_hi;       // regions 0/1 of each step
+  std::vector<int64_t> schur_lo, schur_hi;   // regions 2/3 of each level
   std::vector<int32_t> lvl_step_ptr;         // steps of each level
   double flops = 0.0;
 };

@@ -71,7 +71,6 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
   G.ext_ptr.assign(1, 0);
   G.lvl_step_ptr.assign(1, 0);
   G.panel_ptr.assign(1, 0);
-  G.upd_ptr.assign(1, 0);
   double flops = 0.0;
   for (int32_t L = 0; L < nl; ++L) {
     // A scatter: lower part of the own columns
@@ -105,6 +104,7 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
     for (int32_t s : by_level[L]) maxnc = std::max(maxnc, S.sn[s].nc);
     for (int32_t k0 = 0; k0 < maxnc; k0 += kGfPanel) {
       G.step_k0.push_back(k0);
+      G.upd_lo.push_back((int64_t)G.upd.size());
       G.step_level.push_back(L);
       for (int32_t s : by_level[L]) {
         const Supernode &sn = S.sn[s];
@@ -112,16 +112,30 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
         G.panel_sn.push_back(s);
         const int32_t k1 = std::min(k0 + kGfPanel, sn.nc);
         const int32_t kb = k1 - k0;
-        for (int32_t j0 = k1; j0 < sn.m; j0 += kGfTile)
+        // the rest of the own columns (all rows below the diagonal) and the
+        // own rows of X; the Schur complement waits for the level's end
+        for (int32_t j0 = k1; j0 < sn.nc; j0 += kGfTile)
           for (int32_t i0 = j0; i0 < sn.m; i0 += kGfTile) G.upd.push_back({s, 0, i0, j0});
-        for (int32_t i0 = k1; i0 < sn.m; i0 += kGfTile)
+        for (int32_t i0 = k1; i0 < sn.nc; i0 += kGfTile)
           for (int32_t j0 = 0; j0 < k1; j0 += kGfTile) G.upd.push_back({s, 1, i0, j0});
-        const double t = sn.m - k1;
-        flops += 2.0 * kb * (t * t / 2.0 + t * k1);
+        const double t = sn.nc - k1;
+        flops += 2.0 * kb * (t * (sn.m - k1 - t / 2.0) + t * k1);
       }
       G.panel_ptr.push_back((int64_t)G.panel_sn.size());
-      G.upd_ptr.push_back((int64_t)G.upd.size());
+      G.upd_hi.push_back((int64_t)G.upd.size());
     }
+    // Schur complement and struct rows of X, one pass each (K = nc)
+    G.schur_lo.push_back((int64_t)G.upd.size());
+    for (int32_t s : by_level[L]) {
+      const Supernode &sn = S.sn[s];
+      for (int32_t j0 = sn.nc; j0 < sn.m; j0 += kGfTile)
+        for (int32_t i0 = j0; i0 < sn.m; i0 += kGfTile) G.upd.push_back({s, 2, i0, j0});
+      for (int32_t i0 = sn.nc; i0 < sn.m; i0 += kGfTile)
+        for (int32_t j0 = 0; j0 < sn.nc; j0 += kGfTile) G.upd.push_back({s, 3, i0, j0});
+      const double r = sn.m - sn.nc, c = sn.nc;
+      flops += r * r * c + r * c * c;
+    }
+    G.schur_hi.push_back((int64_t)G.upd.size());
     G.lvl_step_ptr.push_back((int32_t)G.step_k0.size());
   }
   G.flops = flops;

@@ -11,7 +11,10 @@
 //            block to the rows below it (one thread per row, panel values
 //            in registers) and its row operations to the panel rows of X
 //            (one thread per column); then 128 x 128 FP64 FMA tiles update
-//            the trailing lower part of F and the rows of X below the panel
+//            the remaining own columns of F and the own rows of X
+//   schur    once the own columns are done: the Schur complement
+//            F22 -= L21 D L21^T and the struct rows of X, -L21 X_own, in one
+//            pass over each output tile (K = nc)
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave
@@ -68,41 +71,71 @@ __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, const GfFro
 }
 
 // Diagonal block of the panel (columns [k0, k1)) of one front, one workgroup:
-// unblocked LDL^T of the kb x kb block in LDS (diagonal keeps d, below it L).
+// right-looking LDL^T of the kb x kb block in registers.  Thread (tx, ty)
+// of the 16 x 16 grid holds entries (ty + 16a, tx + 16b), a, b < 4, of the
+// lower triangle; at pivot k the owners of column k publish it through LDS
+// (double-buffered, one barrier per pivot) and every thread applies
+//   D[r][c] -= D[r][k] D[c][k] / d_k   (c, r > k, r >= c).
+// Output: d on the diagonal, L = D[r][c] / d_c below it.
 __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_t *sn, int k0,
                                                  double *base, int *status) {
+  static_assert(NB == 64, "thread layout assumes a 64-wide panel");
   const GfFront f = fr[sn[blockIdx.x]];
   const int m = f.m, nc = f.nc;
   const int k1 = min(k0 + NB, nc), kb = k1 - k0;
-  double *F = base + f.offF;
-  __shared__ double D[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < kb * kb; idx += 256) {
-    const int r = idx % kb, c = idx / kb;
-    D[r][c] = r >= c ? F[(int64_t)(k0 + c) * m + k0 + r] : 0.0;
-  }
-  __syncthreads();
+  double *F = base + f.offF + (int64_t)k0 * m + k0;
+  __shared__ double col[2][NB];
+  __shared__ double dg[NB];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double e[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 16 * a, c = tx + 16 * b;
+      e[a][b] = (r < kb && c < kb && r >= c) ? F[(int64_t)c * m + r] : 0.0;
+    }
   for (int k = 0; k < kb; ++k) {
-    double d = D[k][k];
+    double *ck = col[k & 1];
+    if (tx == (k & 15)) {
+      const int bk = k >> 4;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        double x = e[a][0];
+#pragma unroll
+        for (int b = 1; b < 4; ++b) x = bk == b ? e[a][b] : x;
+        ck[ty + 16 * a] = x;
+      }
+    }
+    __syncthreads();
+    double d = ck[k];
     if (!(d > 0.0)) {
-      if (tid == 0) atomicOr(status, 1);
+      if (threadIdx.x == 0) atomicOr(status, 1);
       d = 1.0;  // keep going; the host discards this factor
     }
+    if (threadIdx.x == 0) dg[k] = d;
     const double inv = 1.0 / d;
-    const int w = kb - k - 1;
-    for (int idx = tid; idx < w * w; idx += 256) {
-      const int r = k + 1 + idx / w, c = k + 1 + idx % w;
-      if (c <= r) D[r][c] -= D[r][k] * D[c][k] * inv;
+    double lr[4], cc[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) lr[a] = ck[ty + 16 * a] * inv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cc[b] = ck[tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = ty + 16 * a, c = tx + 16 * b;
+        if (c > k && r >= c) e[a][b] -= lr[a] * cc[b];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = ty + 16 * a, c = tx + 16 * b;
+      if (r < kb && c < kb && r >= c) F[(int64_t)c * m + r] = r == c ? dg[c] : e[a][b] / dg[c];
     }
-    __syncthreads();
-    if (tid > k && tid < kb) D[tid][k] *= inv;
-    if (tid == 0) D[k][k] = d;
-    __syncthreads();
-  }
-  for (int idx = tid; idx < kb * kb; idx += 256) {
-    const int r = idx % kb, c = idx / kb;
-    if (r >= c) F[(int64_t)(k0 + c) * m + k0 + r] = D[r][c];
-  }
 }
 
 // Row operations of one panel step (one launch, two roles; the kb x kb
@@ -181,18 +214,27 @@ __global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int3
   }
 }
 
-// Trailing update of one 128 x 128 tile (8 x 8 outputs per thread, the
-// outputs loaded into the accumulators before the panel is staged):
-//   region 0: F[i, j] -= sum_k L[i, k0+k] W[j, k]        (i >= j >= k1)
-//   region 1: X[i, j] -= sum_k L[i, k0+k] X[k0+k, j]     (i >= k1, j < k1)
-// The panel's k range is staged through LDS 32 columns at a time.
+// One 128 x 128 output tile of an update (regions as in GfTile; 8 x 8
+// outputs per thread, loaded into the accumulators before the first stage).
+// The k range is staged through LDS 32 rows at a time: sA = L[i, k] (rows of
+// the tile), sB = W[j, k], d_k L[j, k] or X[k, j] (columns of the tile).
 __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const GfFront *fr, int k0,
                                                    double *base) {
   constexpr int KC = 32;
   const GfTile t = tiles[blockIdx.x];
   const GfFront f = fr[t.s];
   const int m = f.m, nc = f.nc;
-  const int k1 = min(k0 + NB, nc), kb = k1 - k0;
+  const int reg = t.region;
+  int kbeg, kend, imax, jmax;
+  if (reg == 0) {
+    kbeg = k0, kend = min(k0 + NB, nc), imax = m, jmax = nc;
+  } else if (reg == 1) {
+    kbeg = k0, kend = min(k0 + NB, nc), imax = nc, jmax = kend;
+  } else if (reg == 2) {
+    kbeg = 0, kend = nc, imax = m, jmax = m;
+  } else {
+    kbeg = t.j0, kend = nc, imax = m, jmax = nc;  // X[k, j] = 0 for k < j
+  }
   double *F = base + f.offF;
   double *X = base + f.offX;
   const double *W = base + f.offW;
@@ -201,11 +243,10 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   const int tid = threadIdx.x;
   const int tx = tid & 15, ty = tid >> 4;
   constexpr int R = TL / 16;
-  // region 0: thread rows tx + 16u (consecutive threads -> consecutive rows of
-  // the column-major F); region 1: thread rows ty + 16u, columns tx + 16v
-  // (consecutive threads -> consecutive columns of the row-major X)
-  const bool r0 = t.region == 0;
-  const int ra = r0 ? tx : ty, cb = r0 ? ty : tx;
+  // F outputs (column-major): thread rows tx + 16u, so consecutive threads
+  // touch consecutive rows; X outputs (row-major): thread columns tx + 16v
+  const bool fout = reg == 0 || reg == 2;
+  const int ra = fout ? tx : ty, cb = fout ? ty : tx;
   double acc[R][R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -214,27 +255,24 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
     for (int v = 0; v < R; ++v) {
       const int j = t.j0 + cb + 16 * v;
       double x = 0.0;
-      if (r0) {
-        if (i < m && j < m) x = F[(int64_t)j * m + i];
-      } else {
-        if (i < m && j < k1) x = X[(int64_t)i * nc + j];
-      }
+      if (i < imax && j < jmax) x = fout ? F[(int64_t)j * m + i] : X[(int64_t)i * nc + j];
       acc[u][v] = x;
     }
   }
-  for (int kc0 = 0; kc0 < kb; kc0 += KC) {
-    const int kn = min(KC, kb - kc0);
-    if (kc0 > 0) __syncthreads();
+  for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
+    const int kn = min(KC, kend - kc0);
+    if (kc0 > kbeg) __syncthreads();
     for (int idx = tid; idx < KC * TL; idx += 256) {
       const int k = idx / TL, r = idx % TL;
       const int kk = kc0 + k;
       const int i = t.i0 + r;
-      sA[k][r] = (k < kn && i < m) ? F[(int64_t)(k0 + kk) * m + i] : 0.0;
+      sA[k][r] = (k < kn && i < imax) ? F[(int64_t)kk * m + i] : 0.0;
       const int j = t.j0 + r;
       double b = 0.0;
-      if (k < kn) {
-        if (r0) b = j < m ? W[(int64_t)kk * m + j] : 0.0;
-        else b = j < k1 ? X[(int64_t)(k0 + kk) * nc + j] : 0.0;
+      if (k < kn && j < jmax) {
+        if (reg == 0) b = W[(int64_t)(kk - k0) * m + j];
+        else if (reg == 2) b = F[(int64_t)kk * m + j] * F[(int64_t)kk * m + kk];
+        else b = X[(int64_t)kk * nc + j];
       }
       sB[k][r] = b;
     }
@@ -252,26 +290,18 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
         for (int v = 0; v < R; ++v) acc[u][v] = fma(-a[u], bb[v], acc[u][v]);
     }
   }
-  if (r0) {
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = t.i0 + ra + 16 * u;
 #pragma unroll
     for (int v = 0; v < R; ++v) {
       const int j = t.j0 + cb + 16 * v;
-      if (j >= m) continue;
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        const int i = t.i0 + ra + 16 * u;
-        if (i < m && i >= j) F[(int64_t)j * m + i] = acc[u][v];
-      }
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int i = t.i0 + ra + 16 * u;
-      if (i >= m) continue;
-#pragma unroll
-      for (int v = 0; v < R; ++v) {
-        const int j = t.j0 + cb + 16 * v;
-        if (j < k1) X[(int64_t)i * nc + j] = acc[u][v];
+      if (i < imax && j < jmax) {
+        if (fout) {
+          if (i >= j) F[(int64_t)j * m + i] = acc[u][v];
+        } else {
+          X[(int64_t)i * nc + j] = acc[u][v];
+        }
       }
     }
   }
@@ -336,9 +366,11 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
         k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)np), 256, 0, st>>>(
             d.fr, d.panel_sn + p0, k0, nrb, d.fronts);
       }
-      const int64_t u0 = P.upd_ptr[s], nu = P.upd_ptr[s + 1] - u0;
+      const int64_t u0 = P.upd_lo[s], nu = P.upd_hi[s] - u0;
       if (nu > 0) k_gf_update<<<(unsigned)nu, 256, 0, st>>>(d.upd + u0, d.fr, k0, d.fronts);
     }
+    const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
+    if (nh > 0) k_gf_update<<<(unsigned)nh, 256, 0, st>>>(d.upd + h0, d.fr, 0, d.fronts);
     int64_t maxe = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];

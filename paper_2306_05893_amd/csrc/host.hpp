@@ -4,20 +4,56 @@
 // GPU triangular solves.  Pure C++ (no HIP); compiled with the host compiler.
 #pragma once
 
+#include <sys/mman.h>
+
 #include <cstdint>
+#include <cstdlib>
 #include <functional>
+#include <new>
 #include <string>
 #include <vector>
 
 namespace fe {
+
+// Allocator for the large host arrays of the set-up (triplets, map, pattern):
+// blocks of 64 MiB and more are 2 MiB aligned and asked for transparent huge
+// pages, which cuts the first-touch page faults of multi-GB arrays.
+template <typename T>
+struct HugeAlloc {
+  using value_type = T;
+  static constexpr size_t kBig = size_t(64) << 20, kAlign = size_t(2) << 20;
+  HugeAlloc() = default;
+  template <typename U>
+  HugeAlloc(const HugeAlloc<U> &) {}
+  T *allocate(size_t n) {
+    const size_t bytes = n * sizeof(T);
+    if (bytes < kBig) return static_cast<T *>(::operator new(bytes));
+    const size_t al = (bytes + kAlign - 1) / kAlign * kAlign;
+    void *p = std::aligned_alloc(kAlign, al);
+    if (!p) throw std::bad_alloc();
+    madvise(p, al, MADV_HUGEPAGE);
+    return static_cast<T *>(p);
+  }
+  void deallocate(T *p, size_t n) {
+    if (n * sizeof(T) < kBig) ::operator delete(p);
+    else std::free(p);
+  }
+};
+template <typename T, typename U>
+bool operator==(const HugeAlloc<T> &, const HugeAlloc<U> &) { return true; }
+template <typename T, typename U>
+bool operator!=(const HugeAlloc<T> &, const HugeAlloc<U> &) { return false; }
+template <typename T>
+using hvec = std::vector<T, HugeAlloc<T>>;
 
 // ---------------------------------------------------------------- pattern
 struct Pattern {
   int32_t n_nodes = 0, n_elems = 0, nen = 0;
   int64_t n = 0;                          // DOFs
   std::vector<int32_t> conn;              // [E * nen] element-major copy
-  std::vector<int32_t> row_ptr, col_idx;  // CSR of A (structural, sorted)
-  std::vector<int32_t> tmap;              // canonical map [E * (3 nen)^2]
+  std::vector<int32_t> row_ptr;           // CSR of A (structural, sorted)
+  hvec<int32_t> col_idx;
+  hvec<int32_t> tmap;                     // canonical map [E * (3 nen)^2]
   std::vector<int32_t> fixed_diag_slot;   // CSR slot of (d, d) per fixed DOF
   std::vector<int32_t> fixed_dofs;
   std::vector<uint8_t> fixed;             // [n]
@@ -87,9 +123,13 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
 // eliminated with an augmented block X (m x nc, row-major, starts as the
 // identity on the own rows): the row operations of the elimination turn it
 // into [L11^{-1}; -L21 L11^{-1}], i.e. the explicit-inverse panel.
+// Storage is split by lifetime: the own columns of F, X and W are needed
+// only while the front's level is processed (a per-level arena), the update
+// block (rows and columns >= nc) until the parent's extend-add.
 struct GfFront {
   int32_t m, nc;       // front order and eliminated columns
-  int64_t offF;        // m x m column-major FP64 front (lower part used)
+  int64_t offF;        // own columns: m x nc column-major FP64 (lower part used)
+  int64_t offU;        // update block: (m - nc) x (m - nc) column-major (lower)
   int64_t offX;        // m x nc row-major FP64 augmented block
   int64_t offW;        // m x kGfPanel column-major FP64 panel scratch
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
@@ -114,8 +154,9 @@ constexpr int kGfTile = 128;   // trailing-update tile
 struct GfPlan {
   std::vector<GfFront> fr;                   // by supernode
   int64_t doubles = 0;                       // front storage (FP64 entries)
+  int64_t level_doubles = 0;                 // per-level arena (own columns, X, W)
+  int64_t update_doubles = 0;                // update blocks (first fit)
   std::vector<int32_t> lvl_sn, lvl_ptr;      // supernodes of each level
-  std::vector<int64_t> lvl_lo, lvl_hi;       // storage range of each level
   std::vector<int32_t> a_csr;                // A scatter: CSR slot ...
   std::vector<int64_t> a_off, a_ptr;         // ... -> front entry; per-level ranges
   std::vector<int32_t> parent;               // supernode -> parent (or -1)

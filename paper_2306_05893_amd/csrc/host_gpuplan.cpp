@@ -3,6 +3,7 @@
 // tile lists of the trailing updates.  Built once per topology from the
 // supernodal structure (the same assembly tree as the host factorisation).
 #include <algorithm>
+#include <map>
 
 #include "host.hpp"
 
@@ -17,32 +18,73 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
   std::vector<std::vector<int32_t>> by_level(nl);
   for (int32_t s = 0; s < ns; ++s) by_level[S.sn[s].level].push_back(s);
 
-  // front storage in level order, so that a level is one contiguous range
-  int64_t cur = 0;
+  // Storage.  The per-level arena holds the own columns of F, X and W of
+  // the level's fronts (the next level reuses it: the launches are stream
+  // ordered).  An update block lives from its front's level to its parent's
+  // extend-add; blocks are placed first fit, allocated at the start of their
+  // level and released once the parent level's extend-add has read them.
+  auto round = [](int64_t x) { return (x + 31) / 32 * 32; };
   G.lvl_ptr.assign(1, 0);
+  int64_t arena = 0;
   for (int32_t L = 0; L < nl; ++L) {
-    G.lvl_lo.push_back(cur);
+    int64_t cur = 0;
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
       GfFront &f = G.fr[s];
       f.m = sn.m;
       f.nc = sn.nc;
       f.offF = cur;
-      cur += (int64_t)sn.m * sn.m;
+      cur += round((int64_t)sn.m * sn.nc);
       f.offX = cur;
-      cur += (int64_t)sn.m * sn.nc;
+      cur += round((int64_t)sn.m * sn.nc);
       f.offW = cur;
-      cur += (int64_t)sn.m * kGfPanel;
-      cur = (cur + 31) / 32 * 32;
+      cur += round((int64_t)sn.m * kGfPanel);
       f.rows_off = sn.rows_off;
       f.panel_off = sn.panel_off;
       G.lvl_sn.push_back(s);
       G.parent[s] = sn.parent;
     }
-    G.lvl_hi.push_back(cur);
+    arena = std::max(arena, cur);
     G.lvl_ptr.push_back((int32_t)G.lvl_sn.size());
   }
-  G.doubles = cur;
+  std::map<int64_t, int64_t> free_blocks;  // offset -> size, coalesced
+  int64_t top = 0;
+  auto alloc = [&](int64_t n) -> int64_t {
+    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it)
+      if (it->second >= n) {
+        const int64_t o = it->first, rest = it->second - n;
+        free_blocks.erase(it);
+        if (rest > 0) free_blocks[o + n] = rest;
+        return o;
+      }
+    const int64_t o = top;
+    top += n;
+    return o;
+  };
+  auto release = [&](int64_t o, int64_t n) {
+    auto it = free_blocks.emplace(o, n).first;
+    auto nx = std::next(it);
+    if (nx != free_blocks.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_blocks.erase(nx);
+    }
+    if (it != free_blocks.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_blocks.erase(it);
+      }
+    }
+  };
+  auto ublock = [&](int32_t s) { return round((int64_t)(S.sn[s].m - S.sn[s].nc) * (S.sn[s].m - S.sn[s].nc)); };
+  for (int32_t L = 0; L < nl; ++L) {
+    for (int32_t s : by_level[L]) G.fr[s].offU = arena + alloc(std::max<int64_t>(ublock(s), 32));
+    for (int32_t s : by_level[L])
+      for (int32_t c : S.children[s]) release(G.fr[c].offU - arena, std::max<int64_t>(ublock(c), 32));
+  }
+  G.level_doubles = arena;
+  G.update_doubles = top;
+  G.doubles = arena + top;
 
   // front position of every panel row, per supernode (DOF -> row)
   std::vector<int32_t> pos(P.n, -1);

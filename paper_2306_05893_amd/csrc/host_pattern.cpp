@@ -43,6 +43,7 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
   const int ne = 3 * nen;                 // element DOFs
   const int64_t per_elem = (int64_t)ne * ne;
   const int64_t T = per_elem * n_elems;   // triplets
+  if (T > INT32_MAX) return "too many triplets for int32 indices";
   auto key_row = [&](int64_t t) {
     const int64_t e = t / per_elem, ij = t % per_elem;
     const int i = (int)(ij / ne);
@@ -62,8 +63,8 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
   }
   for (int64_t c = 0; c < n; ++c) ptr1[c + 1] += ptr1[c];
   const int64_t T1 = ptr1[n];
-  std::vector<int32_t> t1_row(T1);   // row of X for each entry of X^T
-  std::vector<int64_t> t1_id(T1);    // triplet index (fill order)
+  hvec<int32_t> t1_row(T1);   // row of X for each entry of X^T
+  hvec<int32_t> t1_id(T1);    // triplet index (fill order)
   {
     std::vector<int64_t> fill(ptr1.begin(), ptr1.end() - 1);
     for (int64_t t = 0; t < T; ++t) {
@@ -71,7 +72,7 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
       if (P.fixed[c]) continue;
       const int64_t pos = fill[c]++;
       t1_row[pos] = key_row(t);
-      t1_id[pos] = t;
+      t1_id[pos] = (int32_t)t;
     }
   }
 
@@ -82,8 +83,8 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
     if (!P.fixed[t1_row[k]]) ++ptr2[t1_row[k] + 1];
   for (int64_t r = 0; r < n; ++r) ptr2[r + 1] += ptr2[r];
   const int64_t T2 = ptr2[n];
-  std::vector<int32_t> t2_col(T2);
-  std::vector<int64_t> t2_id(T2);
+  hvec<int32_t> t2_col(T2);
+  hvec<int32_t> t2_id(T2);
   {
     std::vector<int64_t> fill(ptr2.begin(), ptr2.end() - 1);
     for (int64_t c = 0; c < n; ++c)
@@ -95,8 +96,8 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
         t2_id[pos] = t1_id[k];
       }
   }
-  std::vector<int32_t>().swap(t1_row);
-  std::vector<int64_t>().swap(t1_id);
+  hvec<int32_t>().swap(t1_row);
+  hvec<int32_t>().swap(t1_id);
 
   // ---- merge duplicates into CSR and record the map
   P.tmap.assign(T, -1);

@@ -30,15 +30,16 @@ namespace {
 constexpr int NB = kGfPanel;
 constexpr int TL = kGfTile;
 
-__global__ void k_gf_zero(int64_t n, double *p) {
+// Start of a level: own columns and update block of F zeroed, X = [I; 0].
+// blockIdx.y = front of the level, grid-stride over its entries.
+__global__ void k_gf_init(const GfFront *fr, const int32_t *sn, double *base) {
+  const GfFront f = fr[sn[blockIdx.y]];
+  const int64_t nF = (int64_t)f.m * f.nc, r = f.m - f.nc, nU = r * r;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
-}
-
-// X = identity on the own rows (one block per front)
-__global__ void k_gf_xdiag(const GfFront *fr, const int32_t *sn, double *base) {
-  const GfFront f = fr[sn[blockIdx.x]];
-  for (int i = threadIdx.x; i < f.nc; i += blockDim.x) base[f.offX + (int64_t)i * f.nc + i] = 1.0;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < nF; i += stride) base[f.offF + i] = 0.0;
+  for (int64_t i = i0; i < nU; i += stride) base[f.offU + i] = 0.0;
+  for (int64_t i = i0; i < nF; i += stride) base[f.offX + i] = (i / f.nc == i % f.nc) ? 1.0 : 0.0;
 }
 
 template <typename TA>
@@ -61,12 +62,16 @@ __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, const GfFro
   const int ii = t.i0 + tx;
   if (ii >= nr) return;
   const int pi = rl[ii];
+  const int rp = fp.m - fp.nc;
   for (int jj = t.j0 + ty; jj < min(t.j0 + 32, nr); jj += 8) {
     if (ii < jj) continue;
-    const double u = base[fc.offF + (int64_t)(fc.nc + jj) * fc.m + fc.nc + ii];
+    const double u = base[fc.offU + (int64_t)jj * nr + ii];
     const int pj = rl[jj];
-    const int64_t o = pi >= pj ? (int64_t)pj * fp.m + pi : (int64_t)pi * fp.m + pj;
-    atomicAdd(base + fp.offF + o, u);
+    const int hi = max(pi, pj), lo = min(pi, pj);
+    // own columns of the parent, or its update block
+    const int64_t o = lo < fp.nc ? fp.offF + (int64_t)lo * fp.m + hi
+                                 : fp.offU + (int64_t)(lo - fp.nc) * rp + (hi - fp.nc);
+    atomicAdd(base + o, u);
   }
 }
 
@@ -238,6 +243,8 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   double *F = base + f.offF;
   double *X = base + f.offX;
   const double *W = base + f.offW;
+  double *U = base + f.offU;  // region 2: entry (i, j) at (j - nc) * (m - nc) + i - nc
+  const int64_t ru = m - nc;
   __shared__ double sA[KC][TL + 2];
   __shared__ double sB[KC][TL + 2];
   const int tid = threadIdx.x;
@@ -255,7 +262,10 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
     for (int v = 0; v < R; ++v) {
       const int j = t.j0 + cb + 16 * v;
       double x = 0.0;
-      if (i < imax && j < jmax) x = fout ? F[(int64_t)j * m + i] : X[(int64_t)i * nc + j];
+      if (i < imax && j < jmax)
+        x = reg == 0 ? F[(int64_t)j * m + i]
+            : reg == 2 ? U[(j - nc) * ru + (i - nc)]
+                       : X[(int64_t)i * nc + j];
       acc[u][v] = x;
     }
   }
@@ -298,7 +308,10 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
       const int j = t.j0 + cb + 16 * v;
       if (i < imax && j < jmax) {
         if (fout) {
-          if (i >= j) F[(int64_t)j * m + i] = acc[u][v];
+          if (i >= j) {
+            if (reg == 0) F[(int64_t)j * m + i] = acc[u][v];
+            else U[(j - nc) * ru + (i - nc)] = acc[u][v];
+          }
         } else {
           X[(int64_t)i * nc + j] = acc[u][v];
         }
@@ -335,14 +348,18 @@ __global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_
 template <typename TA, typename T>
 void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA *A, T *panels,
                        T *dinv) {
-  const int nl = (int)P.lvl_lo.size();
+  const int nl = (int)P.lvl_ptr.size() - 1;
   for (int L = 0; L < nl; ++L) {
     const int f0 = P.lvl_ptr[L], nf = P.lvl_ptr[L + 1] - f0;
     if (nf == 0) continue;
-    const int64_t nz = P.lvl_hi[L] - P.lvl_lo[L];
-    const int64_t zb = std::min<int64_t>((nz + 255) / 256, 16384);
-    k_gf_zero<<<(unsigned)zb, 256, 0, st>>>(nz, d.fronts + P.lvl_lo[L]);
-    k_gf_xdiag<<<nf, 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts);
+    int64_t maxz = 0;
+    for (int k = f0; k < f0 + nf; ++k) {
+      const GfFront &g = P.fr[P.lvl_sn[k]];
+      maxz = std::max<int64_t>(maxz, std::max<int64_t>((int64_t)g.m * g.nc,
+                                                       (int64_t)(g.m - g.nc) * (g.m - g.nc)));
+    }
+    const unsigned zx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxz + 255) / 256, 512));
+    k_gf_init<<<dim3(zx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts);
     const int64_t a0 = P.a_ptr[L], na = P.a_ptr[L + 1] - a0;
     if (na > 0)
       k_gf_scatter<TA><<<(unsigned)((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0,

@@ -48,16 +48,27 @@ struct ElemParams {
 template <typename T>
 void launch_assembly_init(hipStream_t st, int64_t nnz, T *A, int64_t n_fixed,
                           const int32_t *fixed_diag_slot, int64_t n, double *b,
-                          const double *f_nodal, const uint8_t *dof_fixed);
+                          const double *f_nodal, const uint8_t *dof_fixed, bool zero_A);
 
-// Element tangents + forces, scattered into A (CSR) and b.
-//   slot: compact map [E][nen*nen] (1 byte) or NULL with smap [E][(3nen)^2]
+// Element tangents + forces.  With the compact map (slot != NULL) the 3 x 3
+// blocks go to ebuf [E][nen*nen][9] and the RHS shares of the nodes to rbuf
+// [E][nen][3] (no atomics; launch_assembly_gather sums them into A and b);
+// otherwise (smap [E][(3nen)^2]) they are added into A and b with atomics.
 template <typename T>
 void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_t *conn,
                     const uint8_t *slot, const int32_t *smap, const int32_t *row_ptr,
                     const double *X, const double *q, const double *v, const double *E,
                     const uint8_t *dof_fixed, const ElemParams &prm, T *A, double *b,
-                    PcgState *state);
+                    T *ebuf, double *rbuf, PcgState *state);
+
+// Sum of the element contributions per node block of A (one thread per
+// block, contributions in element order) and, on diagonal blocks, of the
+// RHS shares of the row node: b = f_nodal + sum.
+template <typename T>
+void launch_assembly_gather(hipStream_t st, int nen, int64_t n_blocks, const int32_t *blk_ptr,
+                            const int32_t *blk_src, const int32_t *blk_pos,
+                            const int32_t *blk_node, const int32_t *row_ptr, const T *ebuf,
+                            const double *rbuf, const double *f_nodal, T *A, double *b);
 
 // y = A x; if dot_partial != NULL also sum_i w[i] y[i] per block.
 template <typename T>

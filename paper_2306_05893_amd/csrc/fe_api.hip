@@ -80,6 +80,10 @@ struct fe_ctx {
   int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_conn = nullptr, *d_smap = nullptr,
           *d_fds = nullptr, *d_rows = nullptr;
   uint8_t *d_slot = nullptr, *d_dof_fixed = nullptr;
+  // assembly without atomics: block lists and the element contribution buffers
+  int32_t *d_blk_ptr = nullptr, *d_blk_pos = nullptr, *d_blk_node = nullptr, *d_blk_src = nullptr;
+  void *d_ebuf = nullptr;
+  double *d_rbuf = nullptr;
   double *d_X = nullptr;
   SnDev *d_sn = nullptr;
   TileDev *d_ftiles = nullptr, *d_btiles = nullptr;
@@ -174,7 +178,7 @@ enum {
   L_PAN0, L_PAN1, L_DINV0, L_DINV1, L_JDINV, L_R, L_Z, L_P, L_Q, L_TMP, L_B, L_ACC, L_ABAR,
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
-  L_GF_UPD, L_GF_ASNAP, L_GF_STATUS
+  L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -224,6 +228,14 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(g ? (int64_t)Gp.upd.size() * (int64_t)sizeof(GfTile) : 0);
   L.add(g ? nnz * ts : 0);
   L.add(g ? 256 : 0);
+  const bool cg = P.compact_ok;
+  const int64_t nen = P.nen;
+  L.add(cg ? (int64_t)P.blk_ptr.size() * 4 : 0);
+  L.add(cg ? (int64_t)P.blk_pos.size() * 4 : 0);
+  L.add(cg ? (int64_t)P.blk_node.size() * 4 : 0);
+  L.add(cg ? (int64_t)P.blk_src.size() * 4 : 0);
+  L.add(cg ? (int64_t)P.n_elems * nen * nen * 9 * ts : 0);
+  L.add(cg ? (int64_t)P.n_elems * nen * 3 * 8 : 0);
   return L;
 }
 
@@ -549,16 +561,22 @@ template <typename T>
 int assemble(fe_ctx *c, const fe_params *p, const double *q, const double *v, T *A, double *b,
              hipStream_t st) {
   const ElemParams ep = to_elem(p);
+  const bool gather = c->P.compact_ok;
   launch_assembly_init<T>(st, (int64_t)c->P.col_idx.size(), A,
                           (int64_t)c->P.fixed_diag_slot.size(), c->d_fds, c->P.n, b,
-                          p->f_nodal, c->d_dof_fixed);
+                          p->f_nodal, c->d_dof_fixed, !gather);
   const double bytes = (double)c->P.col_idx.size() * sizeof(T) + 8.0 * c->P.n +
                        (4.0 * c->nen + 8.0 + (c->P.compact_ok ? c->nen * c->nen : 36.0 * c->nen * c->nen)) *
                            c->P.n_elems + 72.0 * c->P.n_nodes;
   TimedLaunch tl(c, st, 3, bytes);
   launch_element<T>(st, c->elem_type, c->P.n_elems, c->d_conn,
                     c->P.compact_ok ? c->d_slot : nullptr, c->P.compact_ok ? nullptr : c->d_smap,
-                    c->d_row_ptr, c->d_X, q, v, p->E, c->d_dof_fixed, ep, A, b, c->d_state);
+                    c->d_row_ptr, c->d_X, q, v, p->E, c->d_dof_fixed, ep, A, b,
+                    static_cast<T *>(c->d_ebuf), c->d_rbuf, c->d_state);
+  if (gather)
+    launch_assembly_gather<T>(st, c->nen, (int64_t)c->P.blk_pos.size(), c->d_blk_ptr,
+                              c->d_blk_src, c->d_blk_pos, c->d_blk_node, c->d_row_ptr,
+                              static_cast<const T *>(c->d_ebuf), c->d_rbuf, p->f_nodal, A, b);
   return FE_OK;
 }
 
@@ -972,6 +990,12 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_conn = ptr_at<int32_t>(w, L, L_CONN);
   c->d_slot = ptr_at<uint8_t>(w, L, L_SLOT);
   c->d_smap = ptr_at<int32_t>(w, L, L_SMAP);
+  c->d_blk_ptr = ptr_at<int32_t>(w, L, L_BLKPTR);
+  c->d_blk_pos = ptr_at<int32_t>(w, L, L_BLKPOS);
+  c->d_blk_node = ptr_at<int32_t>(w, L, L_BLKNODE);
+  c->d_blk_src = ptr_at<int32_t>(w, L, L_BLKSRC);
+  c->d_ebuf = w + L.off[L_EBUF];
+  c->d_rbuf = ptr_at<double>(w, L, L_RBUF);
   c->d_fds = ptr_at<int32_t>(w, L, L_FDS);
   c->d_dof_fixed = ptr_at<uint8_t>(w, L, L_DOFFIX);
   c->d_X = ptr_at<double>(w, L, L_X);
@@ -1030,8 +1054,15 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   HIP_TRY(up(c->d_row_ptr, P.row_ptr.data(), P.row_ptr.size() * 4));
   HIP_TRY(up(c->d_col, P.col_idx.data(), P.col_idx.size() * 4));
   HIP_TRY(up(c->d_conn, P.conn.data(), P.conn.size() * 4));
-  if (P.compact_ok) HIP_TRY(up(c->d_slot, P.slot.data(), P.slot.size()));
-  else HIP_TRY(up(c->d_smap, P.tmap.data(), P.tmap.size() * 4));
+  if (P.compact_ok) {
+    HIP_TRY(up(c->d_slot, P.slot.data(), P.slot.size()));
+    HIP_TRY(up(c->d_blk_ptr, P.blk_ptr.data(), P.blk_ptr.size() * 4));
+    HIP_TRY(up(c->d_blk_pos, P.blk_pos.data(), P.blk_pos.size() * 4));
+    HIP_TRY(up(c->d_blk_node, P.blk_node.data(), P.blk_node.size() * 4));
+    HIP_TRY(up(c->d_blk_src, P.blk_src.data(), P.blk_src.size() * 4));
+  } else {
+    HIP_TRY(up(c->d_smap, P.tmap.data(), P.tmap.size() * 4));
+  }
   HIP_TRY(up(c->d_fds, P.fixed_diag_slot.data(), P.fixed_diag_slot.size() * 4));
   HIP_TRY(up(c->d_dof_fixed, P.fixed.data(), P.fixed.size()));
   HIP_TRY(up(c->d_X, c->X.data(), c->X.size() * 8));

@@ -63,6 +63,13 @@ struct Pattern {
   bool compact_ok = false;
   std::vector<uint8_t> slot;
   std::vector<uint8_t> node_fixed;        // [n_nodes], 1 = all DOFs fixed
+  // Inverse of the compact map, for an assembly without atomics: the 3 x 3
+  // node blocks of the free rows of A (block = (row node, slot)), each with
+  // the list of element contributions e * nen^2 + a * nen + b that fall on
+  // it, in element order.  blk_pos = CSR position of the block's entry
+  // (0, 0); blk_node = row node, with bit 31 set on diagonal blocks.
+  std::vector<int32_t> blk_ptr, blk_pos, blk_node;
+  hvec<int32_t> blk_src;
 };
 
 // Two counting-sort transposes + merge (paper Sec. 4.2, Sec. 6.1).

@@ -156,6 +156,38 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
     P.compact_ok = ok;
     if (!ok) std::vector<uint8_t>().swap(P.slot);
   }
+
+  // ---- inverse of the compact map: contributions per node block
+  if (P.compact_ok) {
+    std::vector<int32_t> blk0(n_nodes + 1, 0);  // first block of each row node
+    for (int32_t g = 0; g < n_nodes; ++g)
+      blk0[g + 1] = blk0[g] + (P.node_fixed[g] ? 0 : (P.row_ptr[3 * g + 1] - P.row_ptr[3 * g]) / 3);
+    const int32_t nb = blk0[n_nodes];
+    P.blk_pos.resize(nb);
+    P.blk_node.resize(nb);
+    for (int32_t g = 0; g < n_nodes; ++g)
+      for (int32_t k = blk0[g]; k < blk0[g + 1]; ++k) {
+        const int32_t pos = P.row_ptr[3 * g] + 3 * (k - blk0[g]);
+        P.blk_pos[k] = pos;
+        const bool diag = P.col_idx[pos] == 3 * g;
+        P.blk_node[k] = (int32_t)((uint32_t)g | (diag ? 0x80000000u : 0u));
+      }
+    const int nn = nen * nen;
+    P.blk_ptr.assign(nb + 1, 0);
+    for (int64_t e = 0; e < n_elems; ++e)
+      for (int ab = 0; ab < nn; ++ab) {
+        const uint8_t s = P.slot[e * nn + ab];
+        if (s != 0xFF) ++P.blk_ptr[blk0[conn[e * nen + ab / nen]] + s + 1];
+      }
+    for (int32_t k = 0; k < nb; ++k) P.blk_ptr[k + 1] += P.blk_ptr[k];
+    P.blk_src.resize(P.blk_ptr[nb]);
+    std::vector<int32_t> fill(P.blk_ptr.begin(), P.blk_ptr.end() - 1);
+    for (int64_t e = 0; e < n_elems; ++e)
+      for (int ab = 0; ab < nn; ++ab) {
+        const uint8_t s = P.slot[e * nn + ab];
+        if (s != 0xFF) P.blk_src[fill[blk0[conn[e * nen + ab / nen]] + s]++] = (int32_t)(e * nn + ab);
+      }
+  }
   return "";
 }
 

@@ -171,24 +171,23 @@ template <typename T, bool COMPACT, int NEN>
 __device__ inline void scatter(int64_t e, int a, int b, int ga, const T *Ablk, const T *rhs,
                                const uint8_t *slot, const int32_t *smap,
                                const int32_t *row_ptr, const uint8_t *dof_fixed, T *A,
-                               double *bvec) {
+                               double *bvec, T *ebuf, double *rbuf) {
   // RHS: sum over the NEN lanes that share node a (consecutive lanes)
   double r3[3] = {(double)rhs[0], (double)rhs[1], (double)rhs[2]};
   for (int off = 1; off < NEN; off <<= 1)
     for (int r = 0; r < 3; ++r) r3[r] += __shfl_xor(r3[r], off, NEN);
-  if (b == 0)
-    for (int r = 0; r < 3; ++r) {
-      const int dof = 3 * ga + r;
-      if (!dof_fixed[dof]) atomicAdd(bvec + dof, r3[r]);
-    }
   if (COMPACT) {
-    const uint8_t s = slot[e * (NEN * NEN) + a * NEN + b];
-    if (s != 0xFF)
-      for (int r = 0; r < 3; ++r) {
-        T *dst = A + row_ptr[3 * ga + r] + 3 * (int)s;
-        for (int c = 0; c < 3; ++c) atomic_add_t(dst + c, Ablk[r * 3 + c]);
-      }
+    // contribution buffers, summed per node block by the gather kernel
+    T *dst = ebuf + (e * (NEN * NEN) + a * NEN + b) * 9;
+    for (int k = 0; k < 9; ++k) dst[k] = Ablk[k];
+    if (b == 0)
+      for (int r = 0; r < 3; ++r) rbuf[(e * NEN + a) * 3 + r] = r3[r];
   } else {
+    if (b == 0)
+      for (int r = 0; r < 3; ++r) {
+        const int dof = 3 * ga + r;
+        if (!dof_fixed[dof]) atomicAdd(bvec + dof, r3[r]);
+      }
     const int ne = 3 * NEN;
     const int32_t *m = smap + e * (int64_t)(ne * ne);
     for (int r = 0; r < 3; ++r)
@@ -206,7 +205,8 @@ __global__ __launch_bounds__(256) void k_elem_hex(
     const int32_t *__restrict__ smap, const int32_t *__restrict__ row_ptr,
     const double *__restrict__ X, const double *__restrict__ q, const double *__restrict__ v,
     const double *__restrict__ Ev, const uint8_t *__restrict__ dof_fixed, ElemParams prm,
-    T *__restrict__ A, double *__restrict__ bvec, PcgState *state) {
+    T *__restrict__ A, double *__restrict__ bvec, T *__restrict__ ebuf,
+    double *__restrict__ rbuf, PcgState *state) {
   constexpr int NW = 4;
   __shared__ T s_x[NW][8][3], s_u[NW][8][3], s_v[NW][8][3];
   __shared__ T s_g[NW][8][8][3], s_h[NW][8][8][3];
@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void k_elem_hex(
     rhs[i] = Mab * grav[i] - fa[i] - al * Mab * vb[i] - cKv * kv;
   }
   scatter<T, COMPACT, 8>(e, a, b, s_node[w][a], Ablk, rhs, slot, smap, row_ptr, dof_fixed, A,
-                         bvec);
+                         bvec, ebuf, rbuf);
 }
 
 // ------------------------------------------------------------------ TET4
@@ -325,7 +325,8 @@ __global__ __launch_bounds__(256) void k_elem_tet(
     const int32_t *__restrict__ smap, const int32_t *__restrict__ row_ptr,
     const double *__restrict__ X, const double *__restrict__ q, const double *__restrict__ v,
     const double *__restrict__ Ev, const uint8_t *__restrict__ dof_fixed, ElemParams prm,
-    T *__restrict__ A, double *__restrict__ bvec, PcgState *state) {
+    T *__restrict__ A, double *__restrict__ bvec, T *__restrict__ ebuf,
+    double *__restrict__ rbuf, PcgState *state) {
   constexpr int NT = 16;  // tets per block
   __shared__ T s_x[NT][4][3], s_u[NT][4][3], s_v[NT][4][3];
   __shared__ int s_node[NT][4];
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(256) void k_elem_tet(
     rhs[i] = Mab * grav[i] - fa[i] - al * Mab * vb[i] - cKv * kv;
   }
   scatter<T, COMPACT, 4>(e, a, b, s_node[t][a], Ablk, rhs, slot, smap, row_ptr, dof_fixed, A,
-                         bvec);
+                         bvec, ebuf, rbuf);
 }
 
 template <typename T>
@@ -407,6 +408,47 @@ __global__ void k_assembly_init(int64_t nnz, T *A, int64_t n_fixed, const int32_
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) A[k] = T(0);
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
     b[k] = dof_fixed[k] ? 0.0 : (f_nodal ? f_nodal[k] : 0.0);
+}
+
+// One thread per node block: A entries (r, c) at blk_pos + r * L + c, L =
+// the row length of the row node (its three rows share one column set).
+template <typename T, int NEN>
+__global__ void k_assembly_gather(int64_t n_blocks, const int32_t *__restrict__ blk_ptr,
+                                  const int32_t *__restrict__ blk_src,
+                                  const int32_t *__restrict__ blk_pos,
+                                  const int32_t *__restrict__ blk_node,
+                                  const int32_t *__restrict__ row_ptr, const T *__restrict__ ebuf,
+                                  const double *__restrict__ rbuf,
+                                  const double *__restrict__ f_nodal, T *__restrict__ A,
+                                  double *__restrict__ b) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_blocks) return;
+  const int32_t info = blk_node[k];
+  const int g = info & 0x7fffffff;
+  const bool diag = info < 0;
+  const int32_t pos = blk_pos[k];
+  const int32_t L = row_ptr[3 * g + 1] - row_ptr[3 * g];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double br[3] = {0, 0, 0};
+  for (int32_t j = blk_ptr[k]; j < blk_ptr[k + 1]; ++j) {
+    const int32_t src = blk_src[j];
+    const T *eb = ebuf + (int64_t)src * 9;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] += (double)eb[q];
+    if (diag) {
+      // src = e * NEN^2 + a * NEN + a: the RHS share of node a of element e
+      const int64_t ea = (int64_t)(src / (NEN * NEN)) * NEN + (src % (NEN * NEN)) / NEN;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) br[r] += rbuf[ea * 3 + r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A[pos + r * L + c] = (T)acc[r * 3 + c];
+  if (diag)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) b[3 * g + r] = (f_nodal ? f_nodal[3 * g + r] : 0.0) + br[r];
 }
 
 template <typename T>
@@ -420,7 +462,8 @@ __global__ void k_set_fixed_diag(int64_t n_fixed, const int32_t *fds, T *A) {
 template <typename T>
 void launch_assembly_init(hipStream_t st, int64_t nnz, T *A, int64_t n_fixed,
                           const int32_t *fds, int64_t n, double *b, const double *f_nodal,
-                          const uint8_t *dof_fixed) {
+                          const uint8_t *dof_fixed, bool zero_A) {
+  if (!zero_A) nnz = 0;  // every free-row entry is written by the gather
   const int64_t work = nnz > n ? nnz : n;
   int64_t blocks = (work + 255) / 256;
   if (blocks > 8192) blocks = 8192;
@@ -434,14 +477,14 @@ void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_
                     const uint8_t *slot, const int32_t *smap, const int32_t *row_ptr,
                     const double *X, const double *q, const double *v, const double *E,
                     const uint8_t *dof_fixed, const ElemParams &prm, T *A, double *b,
-                    PcgState *state) {
+                    T *ebuf, double *rbuf, PcgState *state) {
   if (n_elems <= 0) return;
   const bool compact = slot != nullptr;
   if (elem_type == 8) {
     const unsigned blocks = (unsigned)((n_elems + 3) / 4);
 #define FE_HEX(MAT, CMP)                                                                    \
   k_elem_hex<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
-                                                   v, E, dof_fixed, prm, A, b, state)
+                                                   v, E, dof_fixed, prm, A, b, ebuf, rbuf, state)
     if (prm.material == 0) {
       if (compact) FE_HEX(0, true); else FE_HEX(0, false);
     } else {
@@ -452,7 +495,7 @@ void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_
     const unsigned blocks = (unsigned)((n_elems + 15) / 16);
 #define FE_TET(MAT, CMP)                                                                    \
   k_elem_tet<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
-                                                   v, E, dof_fixed, prm, A, b, state)
+                                                   v, E, dof_fixed, prm, A, b, ebuf, rbuf, state)
     if (prm.material == 0) {
       if (compact) FE_TET(0, true); else FE_TET(0, false);
     } else {
@@ -462,20 +505,44 @@ void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_
   }
 }
 
+template <typename T>
+void launch_assembly_gather(hipStream_t st, int nen, int64_t n_blocks, const int32_t *blk_ptr,
+                            const int32_t *blk_src, const int32_t *blk_pos,
+                            const int32_t *blk_node, const int32_t *row_ptr, const T *ebuf,
+                            const double *rbuf, const double *f_nodal, T *A, double *b) {
+  if (n_blocks <= 0) return;
+  const unsigned blocks = (unsigned)((n_blocks + 255) / 256);
+  if (nen == 8)
+    k_assembly_gather<T, 8><<<blocks, 256, 0, st>>>(n_blocks, blk_ptr, blk_src, blk_pos, blk_node,
+                                                    row_ptr, ebuf, rbuf, f_nodal, A, b);
+  else
+    k_assembly_gather<T, 4><<<blocks, 256, 0, st>>>(n_blocks, blk_ptr, blk_src, blk_pos, blk_node,
+                                                    row_ptr, ebuf, rbuf, f_nodal, A, b);
+}
+
 template void launch_assembly_init<float>(hipStream_t, int64_t, float *, int64_t, const int32_t *,
-                                          int64_t, double *, const double *, const uint8_t *);
+                                          int64_t, double *, const double *, const uint8_t *,
+                                          bool);
 template void launch_assembly_init<double>(hipStream_t, int64_t, double *, int64_t,
                                            const int32_t *, int64_t, double *, const double *,
-                                           const uint8_t *);
+                                           const uint8_t *, bool);
+template void launch_assembly_gather<float>(hipStream_t, int, int64_t, const int32_t *,
+                                            const int32_t *, const int32_t *, const int32_t *,
+                                            const int32_t *, const float *, const double *,
+                                            const double *, float *, double *);
+template void launch_assembly_gather<double>(hipStream_t, int, int64_t, const int32_t *,
+                                             const int32_t *, const int32_t *, const int32_t *,
+                                             const int32_t *, const double *, const double *,
+                                             const double *, double *, double *);
 template void launch_element<float>(hipStream_t, int, int64_t, const int32_t *, const uint8_t *,
                                     const int32_t *, const int32_t *, const double *,
                                     const double *, const double *, const double *,
                                     const uint8_t *, const ElemParams &, float *, double *,
-                                    PcgState *);
+                                    float *, double *, PcgState *);
 template void launch_element<double>(hipStream_t, int, int64_t, const int32_t *, const uint8_t *,
                                      const int32_t *, const int32_t *, const double *,
                                      const double *, const double *, const double *,
                                      const uint8_t *, const ElemParams &, double *, double *,
-                                     PcgState *);
+                                     double *, double *, PcgState *);
 
 }  // namespace fe

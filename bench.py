@@ -72,7 +72,8 @@ def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True):
     return out
 
 
-KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd<float>", "trisolve_bwd": "k_tri_bwd<float>",
+# kernel names as rocprofv3 reports them (default tile extents 64 / 512)
+KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd<float, 64>", "trisolve_bwd": "k_tri_bwd<float, 512>",
                  "spmv": "k_spmv<float, 16>", "element": "k_elem_hex<float, 1, true>"}
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "pmc_traffic_hex_beam_mixed.txt")
 

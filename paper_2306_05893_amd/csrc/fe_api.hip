@@ -1030,11 +1030,14 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   // host-side resources
   HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
   memset(c->h_state, 0, sizeof(PcgState));
-  HIP_TRY(hipHostMalloc(&c->h_Asnap, std::max<size_t>(1, c->P.col_idx.size() * c->tsize),
-                        hipHostMallocDefault));
-  HIP_TRY(hipHostMalloc(&c->h_stage,
-                        std::max<size_t>(1, (c->S.panel_entries + c->P.n) * c->tsize),
-                        hipHostMallocDefault));
+  if (!c->gpu_factor) {
+    // snapshot of A and staging of the factor: host-thread factorisation only
+    HIP_TRY(hipHostMalloc(&c->h_Asnap, std::max<size_t>(1, c->P.col_idx.size() * c->tsize),
+                          hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(&c->h_stage,
+                          std::max<size_t>(1, (c->S.panel_entries + c->P.n) * c->tsize),
+                          hipHostMallocDefault));
+  }
   HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&c->ev_snap_ready, hipEventDisableTiming));

@@ -259,7 +259,7 @@ __global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
 }
 
 constexpr int kFR = 256;  // forward tile: 256 rows x TC columns (TC: 16..128)
-constexpr int kBC = 16;   // backward tile: 16 columns x BR rows (BR: 256..1024)
+constexpr int kBC = kBwdCols;  // backward tile: kBC columns x BR rows (BR: 256..1024)
 
 // Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
 // rows (one row per thread, consecutive rows = consecutive addresses of the
@@ -318,9 +318,9 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
 
 // Backward tile: x[rows[j]] += sum_{i in tile rows} G[i, j] v_i with
 // v_i = dinv y (own rows) or -x[rows[i]] (struct rows, already final).
-// Each wavefront handles 4 consecutive columns (lanes stride over rows) and
-// issues all BR/64 x 4 of its panel loads before the inputs v are gathered.
-// Rows above a column's diagonal (zeros of L11^{-1}) are not read.
+// Each wavefront handles CPW consecutive columns (lanes stride over rows)
+// and issues all BR/64 x CPW of its panel loads before the inputs v are
+// gathered.  Rows above a column's diagonal (zeros of L11^{-1}) are not read.
 template <typename T, int BR>
 __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
                                                  const SnDev *__restrict__ sn,
@@ -330,15 +330,15 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
                                                  const T *__restrict__ y, double *z,
                                                  const PcgState *s) {
   if (s && s->done) return;
-  constexpr int NI = BR / 64;
+  constexpr int NI = BR / 64, CPW = kBC / 4;
   __shared__ T s_v[BR];
   const TileDev t = tiles[blockIdx.x];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
   const int r0 = t.r0, r1 = min(d.m, r0 + BR);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int j0 = t.c0 + 4 * wv;
-  const int nj = max(0, min(4, d.nc - j0));
+  const int j0 = t.c0 + CPW * wv;
+  const int nj = max(0, min(CPW, d.nc - j0));
   const int ibeg = max(r0, j0);
   const int64_t m = d.m;
   const T *G = panels + d.panel_off + (int64_t)min(j0, d.nc - 1) * m;
@@ -348,13 +348,13 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   int32_t dof[NV];
 #pragma unroll
   for (int u = 0; u < NV; ++u) dof[u] = rw[min(r0 + (int)threadIdx.x + 256 * u, r1 - 1)];
-  T g[NI][4];
-  if (nj == 4 && ibeg == r0 && r1 == r0 + BR) {
+  T g[NI][CPW];
+  if (nj == CPW && ibeg == r0 && r1 == r0 + BR) {
 #pragma unroll
     for (int q = 0; q < NI; ++q) {
       const int i = r0 + lane + 64 * q;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) g[q][c] = G[c * m + i];
+      for (int c = 0; c < CPW; ++c) g[q][c] = G[c * m + i];
     }
   } else {
 #pragma unroll
@@ -362,7 +362,7 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
       const int i = r0 + lane + 64 * q;
       const bool ok = i >= ibeg && i < r1;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) g[q][c] = (ok && c < nj) ? G[c * m + i] : T(0);
+      for (int c = 0; c < CPW; ++c) g[q][c] = (ok && c < nj) ? G[c * m + i] : T(0);
     }
   }
 #pragma unroll
@@ -374,22 +374,19 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   }
   __syncthreads();
   if (nj == 0 || ibeg >= r1) return;
-  T p0 = T(0), p1 = T(0), p2 = T(0), p3 = T(0);
+  T p[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) p[c] = T(0);
 #pragma unroll
   for (int q = 0; q < NI; ++q) {
     const T v = s_v[lane + 64 * q];
-    p0 += g[q][0] * v;
-    p1 += g[q][1] * v;
-    p2 += g[q][2] * v;
-    p3 += g[q][3] * v;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) p[c] += g[q][c] * v;
   }
-  const double q0 = wave_sum((double)p0), q1 = wave_sum((double)p1);
-  const double q2 = wave_sum((double)p2), q3 = wave_sum((double)p3);
-  if (lane == 0) {
-    atomicAdd(z + rw[j0], q0);
-    if (nj > 1) atomicAdd(z + rw[j0 + 1], q1);
-    if (nj > 2) atomicAdd(z + rw[j0 + 2], q2);
-    if (nj > 3) atomicAdd(z + rw[j0 + 3], q3);
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const double qc = wave_sum((double)p[c]);
+    if (lane == 0 && c < nj) atomicAdd(z + rw[j0 + c], qc);
   }
 }
 

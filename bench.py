@@ -142,6 +142,48 @@ def _adjoint_rate(w, prec, nsteps=10, k=5):
     return nsteps / (t1 - t0), ok
 
 
+def _other_workloads():
+    """The other GPU-sized workloads of the study: the jittered tet block
+    (mixed vs FP64 steps/s) and the 1.39M-DOF two-material hex block (mixed
+    steps/s on its refresh-20 schedule, and per-kernel GB/s, where the panels
+    and A no longer fit the 256 MB last-level cache)."""
+    import synth
+    from paper_2306_05893_amd import FE_PREC_FP64, FE_PREC_MIXED
+
+    out = {}
+    w = synth.make("tet_block")
+    rec = {"n_dofs": w.n_dofs, "refresh": w.refresh}
+    for tag, prec in (("mixed", FE_PREC_MIXED), ("fp64", FE_PREC_FP64)):
+        r = _timed_run(w, prec, 30, 5)
+        r["sim"].ctx.close()
+        rec[tag] = {"steps_per_s": round(r["steps_per_s"], 2),
+                    "cg_it_mean": round(r["cg_it_mean"], 2),
+                    "factor_lag_mean": round(r["factor_lag_mean"], 1)}
+    out["tet_block"] = rec
+    print(f"[bench] tet_block mixed {rec['mixed']['steps_per_s']} / fp64 "
+          f"{rec['fp64']['steps_per_s']} steps/s", file=sys.stderr, flush=True)
+    w = synth.make("hex_block")
+    r = _timed_run(w, FE_PREC_MIXED, 20, 3)
+    kt = _kernel_profile(r["sim"], n_apply=5, n_spmv=20, n_assemble=3)
+    sizes = r["sim"].ctx.sizes
+    r["sim"].ctx.close()
+    kern = {}
+    for name, d in kt.items():
+        if d["count"]:
+            kern[name] = {"avg_us": round(1e3 * d["ms"] / d["count"], 2),
+                          "GBps": round(d["bytes"] / (d["ms"] * 1e-3) / 1e9, 1),
+                          "frac_hbm_peak": round(d["bytes"] / (d["ms"] * 1e-3) / 1e9
+                                                 / HBM_PEAK_GBS, 4)}
+    out["hex_block"] = {"n_dofs": w.n_dofs, "nnz": int(sizes.nnz),
+                        "factor_lower_entries": int(sizes.factor_lower), "refresh": w.refresh,
+                        "steps_per_s": round(r["steps_per_s"], 2),
+                        "cg_it_mean": round(r["cg_it_mean"], 2),
+                        "factor_lag_mean": round(r["factor_lag_mean"], 1), "kernels": kern}
+    print(f"[bench] hex_block {out['hex_block']['steps_per_s']} steps/s", file=sys.stderr,
+          flush=True)
+    return out
+
+
 def _cpu_baseline():
     """Bounded sample of the FP64 oracle on the same workload: one full step
     (element assembly + triplet-sort assembly + banded Cholesky solve +
@@ -247,13 +289,15 @@ def main():
               file=sys.stderr, flush=True)
         adj_rate, adj_ok = _adjoint_rate(w, FE_PREC_MIXED)
         print(f"[bench] adjoint {adj_rate:.1f} steps/s", file=sys.stderr, flush=True)
+        others = _other_workloads()
         extras = {"host_factor_steps_per_s": round(host["steps_per_s"], 3),
                   "host_factor_cg_it_mean": round(host["cg_it_mean"], 2),
                   "host_factor_lag_mean": round(host["factor_lag_mean"], 1),
                   "fp64_steps_per_s": round(fp64["steps_per_s"], 3),
                   "fp64_ms_per_step": round(fp64["ms_per_step"], 4),
                   "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
-                  "adjoint_steps_per_s": round(adj_rate, 3), "adjoint_finite": adj_ok}
+                  "adjoint_steps_per_s": round(adj_rate, 3), "adjoint_finite": adj_ok,
+                  "other_workloads": others}
 
     # per-kernel figures from HIP events recorded around every launch
     kern = {}

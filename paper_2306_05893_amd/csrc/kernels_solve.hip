@@ -37,7 +37,10 @@ __device__ inline double block_sum(double v) {
 }
 
 // ------------------------------------------------------------------- SpMV
-// G lanes per row, FP64 products and row sums of T-valued entries.
+// G lanes per row, FP64 products and row sums of T-valued entries.  Each lane
+// issues the index and value loads of its first U entries at once (clamped
+// to the row, so without branches), then the U gathers of x, so that a row
+// costs three memory latencies; longer rows finish in a loop.
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const int32_t *__restrict__ row_ptr,
                                                  const int32_t *__restrict__ col,
@@ -46,12 +49,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv(int64_t n, const int32_t *__res
                                                  const double *__restrict__ w, double *part,
                                                  const PcgState *state) {
   if (state && state->done) return;
+  constexpr int U = 6;
   const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
   const int sub = threadIdx.x & (G - 1);
   double sum = 0.0;
   if (row < n) {
     const int32_t k0 = row_ptr[row], k1 = row_ptr[row + 1];
-    for (int32_t k = k0 + sub; k < k1; k += G) sum += (double)val[k] * x[col[k]];
+    int32_t c[U];
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t k = min(k0 + sub + u * G, k1 - 1);
+      c[u] = col[k];
+      v[u] = val[k];
+    }
+    double xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (k0 + sub + u * G < k1) sum += (double)v[u] * xv[u];
+    for (int32_t k = k0 + sub + U * G; k < k1; k += G) sum += (double)val[k] * x[col[k]];
   }
   for (int off = G / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, G);
   double d = 0.0;

@@ -93,6 +93,11 @@ typedef struct {
                                  0: host factor thread (the paper's scheme)  */
   int32_t n_threads;          /* host factorisation threads (0: the CPU share:
                                  min(cores, OMP_NUM_THREADS, 16) - 1)         */
+  int32_t factor_max_blocks;  /* GPU factorisation: upper bound on the work-
+                                 groups of one launch (its kernels loop over
+                                 their work), i.e. on the share of the GPU the
+                                 background refactorisation takes from the
+                                 solves; 0: no bound                          */
 } fe_build_opts;
 
 /* Physical parameters of one assembly.  E and f_nodal are DEVICE pointers. */

@@ -138,6 +138,7 @@ struct GfDev {
   const int32_t *rows;
   double *fronts;
   int *status;          // bit 0: non-positive pivot met
+  int max_blocks;       // bound on the workgroups of one launch (0: none)
 };
 // FP64 multifrontal LDL^T of A (values TA) -> explicit-inverse panels and
 // 1/d (T), queued on st.  The plan's host arrays drive the launch sequence.

@@ -121,6 +121,7 @@ struct fe_ctx {
 
   // ---- GPU factorisation (factor_on_gpu)
   bool gpu_factor = false;
+  int gf_max_blocks = 0;
   GfPlan G;
   GfDev gd{};
   void *d_Asnap = nullptr;
@@ -918,6 +919,7 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
     }
     if (e.empty() && opts && opts->factor_on_gpu) {
       c->gpu_factor = true;
+      c->gf_max_blocks = std::max(0, opts->factor_max_blocks);
       e = gpu_plan(c->P, c->S, c->G);
     }
     if (!e.empty()) {
@@ -1129,6 +1131,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
     g.panel_sn = panel_sn;
     g.upd = upd;
     g.rows = c->d_rows;
+    g.max_blocks = c->gf_max_blocks;
     g.status = ptr_at<int>(w, L, L_GF_STATUS);
     c->d_Asnap = w + L.off[L_GF_ASNAP];
     HIP_TRY(hipHostMalloc((void **)&c->h_gf_status, sizeof(int), hipHostMallocDefault));

@@ -31,47 +31,55 @@ constexpr int NB = kGfPanel;
 constexpr int TL = kGfTile;
 
 // Start of a level: own columns and update block of F zeroed, X = [I; 0].
-// blockIdx.y = front of the level, grid-stride over its entries.
-__global__ void k_gf_init(const GfFront *fr, const int32_t *sn, double *base) {
-  const GfFront f = fr[sn[blockIdx.y]];
-  const int64_t nF = (int64_t)f.m * f.nc, r = f.m - f.nc, nU = r * r;
+// Fronts of the level by blockIdx.y (stride gridDim.y), grid-stride over the
+// entries of a front along x.
+__global__ void k_gf_init(const GfFront *fr, const int32_t *sn, int nf, double *base) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int64_t i = i0; i < nF; i += stride) base[f.offF + i] = 0.0;
-  for (int64_t i = i0; i < nU; i += stride) base[f.offU + i] = 0.0;
-  for (int64_t i = i0; i < nF; i += stride) base[f.offX + i] = (i / f.nc == i % f.nc) ? 1.0 : 0.0;
+  for (int q = blockIdx.y; q < nf; q += gridDim.y) {
+    const GfFront f = fr[sn[q]];
+    const int64_t nF = (int64_t)f.m * f.nc, r = f.m - f.nc, nU = r * r;
+    for (int64_t i = i0; i < nF; i += stride) base[f.offF + i] = 0.0;
+    for (int64_t i = i0; i < nU; i += stride) base[f.offU + i] = 0.0;
+    for (int64_t i = i0; i < nF; i += stride) base[f.offX + i] = (i / f.nc == i % f.nc) ? 1.0 : 0.0;
+  }
 }
 
 template <typename TA>
 __global__ void k_gf_scatter(int64_t n, const int32_t *a_csr, const int64_t *a_off, const TA *A,
                              double *base) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) base[a_off[i]] = (double)A[a_csr[i]];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    base[a_off[i]] = (double)A[a_csr[i]];
 }
 
-// extend-add: one 32 x 32 tile of a child's update matrix per block
-__global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, const GfFront *fr,
-                                                   const int32_t *parent, const int32_t *rel,
-                                                   const int64_t *rel_off, double *base) {
-  const GfExt t = ext[blockIdx.x];
-  const GfFront fc = fr[t.child];
-  const GfFront fp = fr[parent[t.child]];
-  const int nr = fc.m - fc.nc;
-  const int32_t *rl = rel + rel_off[t.child];
+// extend-add: 32 x 32 tiles of the children's update matrices (tile per
+// block, stride gridDim.x)
+__global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, int64_t n_ext,
+                                                   const GfFront *fr, const int32_t *parent,
+                                                   const int32_t *rel, const int64_t *rel_off,
+                                                   double *base) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int ii = t.i0 + tx;
-  if (ii >= nr) return;
-  const int pi = rl[ii];
-  const int rp = fp.m - fp.nc;
-  for (int jj = t.j0 + ty; jj < min(t.j0 + 32, nr); jj += 8) {
-    if (ii < jj) continue;
-    const double u = base[fc.offU + (int64_t)jj * nr + ii];
-    const int pj = rl[jj];
-    const int hi = max(pi, pj), lo = min(pi, pj);
-    // own columns of the parent, or its update block
-    const int64_t o = lo < fp.nc ? fp.offF + (int64_t)lo * fp.m + hi
-                                 : fp.offU + (int64_t)(lo - fp.nc) * rp + (hi - fp.nc);
-    atomicAdd(base + o, u);
+  for (int64_t e = blockIdx.x; e < n_ext; e += gridDim.x) {
+    const GfExt t = ext[e];
+    const GfFront fc = fr[t.child];
+    const GfFront fp = fr[parent[t.child]];
+    const int nr = fc.m - fc.nc;
+    const int32_t *rl = rel + rel_off[t.child];
+    const int ii = t.i0 + tx;
+    if (ii >= nr) continue;
+    const int pi = rl[ii];
+    const int rp = fp.m - fp.nc;
+    for (int jj = t.j0 + ty; jj < min(t.j0 + 32, nr); jj += 8) {
+      if (ii < jj) continue;
+      const double u = base[fc.offU + (int64_t)jj * nr + ii];
+      const int pj = rl[jj];
+      const int hi = max(pi, pj), lo = min(pi, pj);
+      // own columns of the parent, or its update block
+      const int64_t o = lo < fp.nc ? fp.offF + (int64_t)lo * fp.m + hi
+                                   : fp.offU + (int64_t)(lo - fp.nc) * rp + (hi - fp.nc);
+      atomicAdd(base + o, u);
+    }
   }
 }
 
@@ -82,10 +90,8 @@ __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, const GfFro
 // (double-buffered, one barrier per pivot) and every thread applies
 //   D[r][c] -= D[r][k] D[c][k] / d_k   (c, r > k, r >= c).
 // Output: d on the diagonal, L = D[r][c] / d_c below it.
-__global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_t *sn, int k0,
-                                                 double *base, int *status) {
+__device__ void gf_diag(const GfFront f, int k0, double *base, int *status) {
   static_assert(NB == 64, "thread layout assumes a 64-wide panel");
-  const GfFront f = fr[sn[blockIdx.x]];
   const int m = f.m, nc = f.nc;
   const int k1 = min(k0 + NB, nc), kb = k1 - k0;
   double *F = base + f.offF + (int64_t)k0 * m + k0;
@@ -143,6 +149,15 @@ __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_
     }
 }
 
+// one front of the step per block (stride gridDim.x)
+__global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_t *sn, int np, int k0,
+                                                 double *base, int *status) {
+  for (int q = blockIdx.x; q < np; q += gridDim.x) {
+    gf_diag(fr[sn[q]], k0, base, status);
+    __syncthreads();
+  }
+}
+
 // Row operations of one panel step (one launch, two roles; the kb x kb
 // diagonal block, already factored, staged in LDS):
 //  * blockIdx.x < nrb: rows below the block, one thread per row with the kb
@@ -152,13 +167,11 @@ __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_
 //    column, forward substitution with the unit lower factor of the block:
 //      x_r <- x_r - sum_{k<r} L_d[r][k] x_k.
 // blockIdx.y = front of the step; chunks of 256 rows / 256 columns.
-__global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int32_t *sn, int k0,
-                                                   int nrb, double *base) {
-  const GfFront f = fr[sn[blockIdx.y]];
+__device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base) {
   const int m = f.m, nc = f.nc;
   const int k1 = min(k0 + NB, nc), kb = k1 - k0;
-  const bool rows_role = (int)blockIdx.x < nrb;
-  const int first = rows_role ? k1 + (int)blockIdx.x * 256 : ((int)blockIdx.x - nrb) * 256;
+  const bool rows_role = bx < nrb;
+  const int first = rows_role ? k1 + bx * 256 : (bx - nrb) * 256;
   if (first >= (rows_role ? m : k1)) return;  // whole block past this front's work
   double *F = base + f.offF;
   // the block, transposed (Lt[k][c] = L_d[c][k], column k of L_d contiguous)
@@ -219,15 +232,21 @@ __global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int3
   }
 }
 
+// blockIdx.x = role chunk, fronts of the step by blockIdx.y (stride gridDim.y)
+__global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int32_t *sn, int np,
+                                                   int k0, int nrb, double *base) {
+  for (int q = blockIdx.y; q < np; q += gridDim.y) {
+    gf_rowops(fr[sn[q]], k0, (int)blockIdx.x, nrb, base);
+    __syncthreads();
+  }
+}
+
 // One 128 x 128 output tile of an update (regions as in GfTile; 8 x 8
 // outputs per thread, loaded into the accumulators before the first stage).
 // The k range is staged through LDS 32 rows at a time: sA = L[i, k] (rows of
 // the tile), sB = W[j, k], d_k L[j, k] or X[k, j] (columns of the tile).
-__global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const GfFront *fr, int k0,
-                                                   double *base) {
+__device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base) {
   constexpr int KC = 32;
-  const GfTile t = tiles[blockIdx.x];
-  const GfFront f = fr[t.s];
   const int m = f.m, nc = f.nc;
   const int reg = t.region;
   int kbeg, kend, imax, jmax;
@@ -320,26 +339,39 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, const Gf
   }
 }
 
-// panel G (m x nc column-major) from X and 1/d; blockIdx.y = front of the level
+// one tile per block (stride gridDim.x)
+__global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, int64_t n_tiles,
+                                                   const GfFront *fr, int k0, double *base) {
+  for (int64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const GfTile t = tiles[q];
+    gf_update(t, fr[t.s], k0, base);
+    __syncthreads();
+  }
+}
+
+// panel G (m x nc column-major) from X and 1/d; fronts of the level by
+// blockIdx.y (stride gridDim.y)
 template <typename T>
-__global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_t *sn,
+__global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_t *sn, int nf,
                                                  const double *base, const int32_t *rows,
                                                  T *panels, T *dinv) {
-  const GfFront f = fr[sn[blockIdx.y]];
-  const int64_t total = (int64_t)f.m * f.nc;
-  const double *X = base + f.offX;
-  T *G = panels + f.panel_off;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-    const int i = (int)(idx % f.m), j = (int)(idx / f.m);
-    const double x = X[(int64_t)i * f.nc + j];
-    G[idx] = (T)(i < f.nc ? x : -x);
-  }
-  if (blockIdx.x == 0) {
-    const int32_t *rw = rows + f.rows_off;
-    const double *F = base + f.offF;
-    for (int k = threadIdx.x; k < f.nc; k += blockDim.x)
-      dinv[rw[k]] = (T)(1.0 / F[(int64_t)k * f.m + k]);
+  for (int q = blockIdx.y; q < nf; q += gridDim.y) {
+    const GfFront f = fr[sn[q]];
+    const int64_t total = (int64_t)f.m * f.nc;
+    const double *X = base + f.offX;
+    T *G = panels + f.panel_off;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+      const int i = (int)(idx % f.m), j = (int)(idx / f.m);
+      const double x = X[(int64_t)i * f.nc + j];
+      G[idx] = (T)(i < f.nc ? x : -x);
+    }
+    if (blockIdx.x == 0) {
+      const int32_t *rw = rows + f.rows_off;
+      const double *F = base + f.offF;
+      for (int k = threadIdx.x; k < f.nc; k += blockDim.x)
+        dinv[rw[k]] = (T)(1.0 / F[(int64_t)k * f.m + k]);
+    }
   }
 }
 
@@ -348,6 +380,14 @@ __global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_
 template <typename TA, typename T>
 void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA *A, T *panels,
                        T *dinv) {
+  // grid of (gx x gy) workgroups for gx x gy work items, within the bound
+  const int64_t cap = d.max_blocks > 0 ? d.max_blocks : INT64_MAX;
+  auto grid1 = [&](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min(n, cap)); };
+  auto grid2 = [&](int64_t gx, int64_t gy) {
+    gx = std::max<int64_t>(1, std::min(gx, cap));
+    gy = std::max<int64_t>(1, std::min(gy, std::max<int64_t>(1, cap / gx)));
+    return dim3((unsigned)gx, (unsigned)std::min<int64_t>(gy, 65535));
+  };
   const int nl = (int)P.lvl_ptr.size() - 1;
   for (int L = 0; L < nl; ++L) {
     const int f0 = P.lvl_ptr[L], nf = P.lvl_ptr[L + 1] - f0;
@@ -358,21 +398,22 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
       maxz = std::max<int64_t>(maxz, std::max<int64_t>((int64_t)g.m * g.nc,
                                                        (int64_t)(g.m - g.nc) * (g.m - g.nc)));
     }
-    const unsigned zx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((maxz + 255) / 256, 512));
-    k_gf_init<<<dim3(zx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts);
+    const int64_t zx = std::max<int64_t>(1, std::min<int64_t>((maxz + 255) / 256, 512));
+    k_gf_init<<<grid2(zx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts);
     const int64_t a0 = P.a_ptr[L], na = P.a_ptr[L + 1] - a0;
     if (na > 0)
-      k_gf_scatter<TA><<<(unsigned)((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0,
-                                                                      A, d.fronts);
+      k_gf_scatter<TA><<<grid1((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0, A,
+                                                                 d.fronts);
     const int64_t e0 = P.ext_ptr[L], ne = P.ext_ptr[L + 1] - e0;
     if (ne > 0)
-      k_gf_extend<<<(unsigned)ne, 256, 0, st>>>(d.ext + e0, d.fr, d.parent, d.rel, d.rel_off,
-                                                d.fronts);
+      k_gf_extend<<<grid1(ne), 256, 0, st>>>(d.ext + e0, ne, d.fr, d.parent, d.rel, d.rel_off,
+                                             d.fronts);
     for (int s = P.lvl_step_ptr[L]; s < P.lvl_step_ptr[L + 1]; ++s) {
       const int k0 = P.step_k0[s];
       const int64_t p0 = P.panel_ptr[s], np = P.panel_ptr[s + 1] - p0;
       if (np > 0) {
-        k_gf_diag<<<(unsigned)np, 256, 0, st>>>(d.fr, d.panel_sn + p0, k0, d.fronts, d.status);
+        k_gf_diag<<<grid1(np), 256, 0, st>>>(d.fr, d.panel_sn + p0, (int)np, k0, d.fronts,
+                                             d.status);
         int maxrows = 0;
         for (int64_t q = p0; q < p0 + np; ++q) {
           const GfFront &g = P.fr[P.panel_sn[q]];
@@ -380,21 +421,24 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
         }
         const int nrb = (maxrows + 255) / 256;
         const int ncb = (k0 + NB + 255) / 256;  // columns [0, k1) of X, k1 <= k0 + NB
-        k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)np), 256, 0, st>>>(
-            d.fr, d.panel_sn + p0, k0, nrb, d.fronts);
+        // the x extent (role chunks) is not bounded: every chunk has its own work
+        const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(np, cap / (nrb + ncb)));
+        k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)std::min<int64_t>(gy, 65535)), 256, 0,
+                      st>>>(d.fr, d.panel_sn + p0, (int)np, k0, nrb, d.fronts);
       }
       const int64_t u0 = P.upd_lo[s], nu = P.upd_hi[s] - u0;
-      if (nu > 0) k_gf_update<<<(unsigned)nu, 256, 0, st>>>(d.upd + u0, d.fr, k0, d.fronts);
+      if (nu > 0) k_gf_update<<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
-    if (nh > 0) k_gf_update<<<(unsigned)nh, 256, 0, st>>>(d.upd + h0, d.fr, 0, d.fronts);
+    if (nh > 0) k_gf_update<<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
     int64_t maxe = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];
       maxe = std::max<int64_t>(maxe, (int64_t)g.m * g.nc);
     }
-    const unsigned gx = (unsigned)std::min<int64_t>((maxe + 255) / 256, 1024);
-    k_gf_emit<T><<<dim3(gx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, d.fronts, d.rows, panels, dinv);
+    const int64_t gx = std::min<int64_t>((maxe + 255) / 256, 1024);
+    k_gf_emit<T><<<grid2(gx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts, d.rows, panels,
+                                                dinv);
   }
 }
 

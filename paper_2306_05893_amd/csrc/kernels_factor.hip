@@ -232,13 +232,10 @@ __device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base
   }
 }
 
-// blockIdx.x = role chunk, fronts of the step by blockIdx.y (stride gridDim.y)
-__global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int32_t *sn, int np,
-                                                   int k0, int nrb, double *base) {
-  for (int q = blockIdx.y; q < np; q += gridDim.y) {
-    gf_rowops(fr[sn[q]], k0, (int)blockIdx.x, nrb, base);
-    __syncthreads();
-  }
+// blockIdx.x = role chunk, blockIdx.y = front of the step
+__global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int32_t *sn, int k0,
+                                                   int nrb, double *base) {
+  gf_rowops(fr[sn[blockIdx.y]], k0, (int)blockIdx.x, nrb, base);
 }
 
 // One 128 x 128 output tile of an update (regions as in GfTile; 8 x 8
@@ -421,10 +418,12 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
         }
         const int nrb = (maxrows + 255) / 256;
         const int ncb = (k0 + NB + 255) / 256;  // columns [0, k1) of X, k1 <= k0 + NB
-        // the x extent (role chunks) is not bounded: every chunk has its own work
-        const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(np, cap / (nrb + ncb)));
-        k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)std::min<int64_t>(gy, 65535)), 256, 0,
-                      st>>>(d.fr, d.panel_sn + p0, (int)np, k0, nrb, d.fronts);
+        // fronts in launches of at most the bound (the role chunks of a front
+        // stay in one launch)
+        const int64_t fy = std::max<int64_t>(1, std::min<int64_t>(65535, cap / (nrb + ncb)));
+        for (int64_t q0 = 0; q0 < np; q0 += fy)
+          k_gf_rowops<<<dim3((unsigned)(nrb + ncb), (unsigned)std::min(fy, np - q0)), 256, 0,
+                        st>>>(d.fr, d.panel_sn + p0 + q0, k0, nrb, d.fronts);
       }
       const int64_t u0 = P.upd_lo[s], nu = P.upd_hi[s] - u0;
       if (nu > 0) k_gf_update<<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);

@@ -184,6 +184,31 @@ def _other_workloads():
     return out
 
 
+def _factor_only(n=5):
+    """Standalone GPU refactorisations of the hex beam (mixed precision, FP64
+    factor), timed one by one: the input of the factorisation kernel profile."""
+    import torch
+
+    import synth
+    from paper_2306_05893_amd import FE_PREC_MIXED
+    from paper_2306_05893_amd.sim import Simulation
+
+    w = synth.make("hex_beam")
+    sim = Simulation(w, prec=FE_PREC_MIXED, device="cuda", factor_on_gpu=True)
+    A, _ = sim.ctx.assemble(sim.params, sim.q, sim.v)
+    ms = []
+    for k in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.ctx.factorize_now(A, k)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    s = sim.ctx.sizes
+    sim.ctx.close()
+    print(json.dumps({"workload": "hex_beam", "factor_ms": [round(x, 3) for x in ms],
+                      "factor_flops": s.factor_flops, "factor_lower_entries": int(s.factor_lower)}))
+
+
 def _cpu_baseline():
     """Bounded sample of the FP64 oracle on the same workload: one full step
     (element assembly + triplet-sort assembly + banded Cholesky solve +
@@ -234,12 +259,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip FP64/adjoint legs")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--factor-only", type=int, default=0, metavar="N",
+                    help="only time N standalone GPU refactorisations of the hex beam")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         _cpu_baseline_child()
+        return
+    if args.factor_only > 0:
+        _factor_only(args.factor_only)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "

@@ -383,12 +383,23 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
       for (int c = 0; c < CPW; ++c) g[q][c] = (ok && c < nj) ? G[c * m + i] : T(0);
     }
   }
+  // inputs: own rows need dinv y, struct rows -x; a tile that lies in one
+  // kind only loads that one (uniform test), a mixed tile loads both
+  const int mode = r0 >= d.nc ? 1 : (r1 <= d.nc ? 0 : 2);
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
     const int k = (int)threadIdx.x + 256 * u, i = r0 + k;
-    const T own = dinv[dof[u]] * y[dof[u]];
-    const T st = (T)(-z[dof[u]]);
-    s_v[k] = i < r1 ? (i < d.nc ? own : st) : T(0);
+    T v;
+    if (mode == 0) {
+      v = dinv[dof[u]] * y[dof[u]];
+    } else if (mode == 1) {
+      v = (T)(-z[dof[u]]);
+    } else {
+      const T own = dinv[dof[u]] * y[dof[u]];
+      const T st = (T)(-z[dof[u]]);
+      v = i < d.nc ? own : st;
+    }
+    s_v[k] = i < r1 ? v : T(0);
   }
   __syncthreads();
   if (nj == 0 || ibeg >= r1) return;

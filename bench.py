@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 
 
-def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True):
+def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True, warm_start=0):
     import torch
 
     from paper_2306_05893_amd import FE_FACTOR_ASYNC, FE_FACTOR_DETERMINISTIC
@@ -42,7 +42,8 @@ def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True):
     sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=gpu_factor)
     det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
                    mode=FE_FACTOR_DETERMINISTIC)
-    asy = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0, mode=FE_FACTOR_ASYNC)
+    asy = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0, mode=FE_FACTOR_ASYNC,
+                   warm_start=warm_start)
     for _ in range(warmup):
         sim.step(det)
     torch.cuda.synchronize()
@@ -317,10 +318,17 @@ def main():
         del host["sim"]
         print(f"[bench] mixed, host factor thread {host['steps_per_s']:.1f} steps/s",
               file=sys.stderr, flush=True)
+        warm = _timed_run(w, FE_PREC_MIXED, args.steps, args.warmup, timing=False, warm_start=1)
+        warm["sim"].ctx.close()
+        del warm["sim"]
+        print(f"[bench] mixed, CG warm start {warm['steps_per_s']:.1f} steps/s", file=sys.stderr,
+              flush=True)
         adj_rate, adj_ok = _adjoint_rate(w, FE_PREC_MIXED)
         print(f"[bench] adjoint {adj_rate:.1f} steps/s", file=sys.stderr, flush=True)
         others = _other_workloads()
-        extras = {"host_factor_steps_per_s": round(host["steps_per_s"], 3),
+        extras = {"warm_start_steps_per_s": round(warm["steps_per_s"], 3),
+                  "warm_start_cg_it_mean": round(warm["cg_it_mean"], 2),
+                  "host_factor_steps_per_s": round(host["steps_per_s"], 3),
                   "host_factor_cg_it_mean": round(host["cg_it_mean"], 2),
                   "host_factor_lag_mean": round(host["factor_lag_mean"], 1),
                   "fp64_steps_per_s": round(fp64["steps_per_s"], 3),

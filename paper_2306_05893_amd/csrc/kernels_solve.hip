@@ -103,9 +103,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *b,
 }
 
 __device__ inline double sum_parts(const double *p, int np) {
-  // one block: fixed-order strided sums then a fixed tree
-  double v = 0.0;
-  for (int i = threadIdx.x; i < np; i += kBlock) v += p[i];
+  // one block: fixed-order strided sums (8 independent accumulators, so that
+  // 8 loads are in flight per thread) then a fixed tree
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 7 * kBlock < np; i += 8 * kBlock)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[i + u * kBlock];
+  for (; i < np; i += kBlock) a[0] += p[i];
+  const double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   return block_sum(v);
 }
 

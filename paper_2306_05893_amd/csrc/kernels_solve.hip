@@ -418,11 +418,21 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
 #pragma unroll
     for (int c = 0; c < CPW; ++c) p[c] += g[q][c] * v;
   }
+  // transpose-reduce of the 4 column partials (fixed order): lanes trade
+  // halves of their columns with lane^1, then lane^2, so that each lane
+  // holds one column summed over 4 lanes, then a butterfly over the rest;
+  // lanes 0..3 end with the totals of columns 2(l&1) + (l>>1&1)
+  static_assert(CPW == 4, "the exchange pattern is for 4 columns per wavefront");
+  const bool odd = lane & 1, b1 = lane & 2;
+  T k0 = odd ? p[2] : p[0], k1 = odd ? p[3] : p[1];
+  k0 += __shfl_xor(odd ? p[0] : p[2], 1);
+  k1 += __shfl_xor(odd ? p[1] : p[3], 1);
+  T tot = b1 ? k1 : k0;
+  tot += __shfl_xor(b1 ? k0 : k1, 2);
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    const double qc = wave_sum((double)p[c]);
-    if (lane == 0 && c < nj) atomicAdd(z + rw[j0 + c], qc);
-  }
+  for (int off = 4; off < 64; off <<= 1) tot += __shfl_xor(tot, off);
+  const int c = (odd ? 2 : 0) + (b1 ? 1 : 0);
+  if (lane < 4 && c < nj) atomicAdd(z + rw[j0 + c], (double)tot);
 }
 
 }  // namespace

@@ -27,6 +27,10 @@ strategy for real-time FE simulations", arXiv 2306.05893):
 * adjoint.py   -- reverse-mode recursion of the step (not in the paper), with
                   the third-derivative term by complex step, and a complex-step
                   derivative of the whole rollout used to pin it.
+* contact.py   -- contact through Lagrange multipliers (Sec. 6.2): the
+                  compliance matrix W = H A^{-1} H^T by one solve with many
+                  right-hand sides, projected Gauss-Seidel on its
+                  complementarity problem, and the motion correction.
 
 Every function is plain and unblocked; vectorisation runs over elements only.
 """

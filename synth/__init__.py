@@ -335,3 +335,48 @@ def random_state(w: Workload, scale: float, seed: int):
 
 def random_vector(n: int, seed: int):
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def contact_constraints(w: Workload, k: int, seed: int, kind: str = "mixed"):
+    """k unilateral contact constraints H x <= delta on the surface y = min of
+    the mesh, as a k x n CSR matrix (row_ptr, col, val), plus delta.
+
+    Stand-in for the paper's contact scenes (a liver falling on rigid planes,
+    about 246 constraints per step): each row is either a node against a
+    slightly tilted rigid plane (3 entries: the plane normal on the node's
+    DOFs) or a rigid point against a surface triangle of three nodes of that
+    face (9 entries: random barycentric weights times the normal).  kind
+    "plane", "triangle" or "mixed" (alternating).  Plane rows use distinct
+    nodes and triangles distinct node triples, so the rows are independent.
+    Only free nodes are used.  delta is N(0, 1) per constraint.
+    """
+    rng = np.random.default_rng(seed)
+    X = w.X
+    ymin = X[:, 1].min()
+    free = ~w.fixed.reshape(-1, 3).any(axis=1)
+    face = np.flatnonzero((np.abs(X[:, 1] - ymin) <= 1e-12) & free)
+    nrm = np.array([0.15, -1.0, 0.1])
+    nrm /= np.linalg.norm(nrm)
+    n_plane = k if kind == "plane" else (0 if kind == "triangle" else (k + 1) // 2)
+    n_tri = k - n_plane
+    if n_plane > face.size or 3 * n_tri > face.size:
+        raise ValueError("not enough free surface nodes for the constraints")
+    plane_nodes = rng.choice(face, n_plane, replace=False)
+    tri_nodes = rng.choice(face, 3 * n_tri, replace=False).reshape(n_tri, 3)
+    row_ptr, col, val = [0], [], []
+    ip = it = 0
+    for a in range(k):
+        use_plane = kind == "plane" or (kind == "mixed" and a % 2 == 0)
+        if use_plane:
+            nodes, wts = plane_nodes[ip:ip + 1], np.ones(1)
+            ip += 1
+        else:
+            nodes, wts = tri_nodes[it], rng.dirichlet(np.ones(3))
+            it += 1
+        for nd, wt in zip(nodes, wts):
+            for c in range(3):
+                col.append(3 * int(nd) + c)
+                val.append(wt * nrm[c])
+        row_ptr.append(len(col))
+    H = (np.asarray(row_ptr, np.int32), np.asarray(col, np.int32), np.asarray(val, np.float64))
+    return H, rng.standard_normal(k)

@@ -256,6 +256,67 @@ int fe_spmv(fe_ctx *ctx, const void *A_vals, const double *x, double *y, void *s
 int fe_precond_apply(fe_ctx *ctx, const void *A_vals, const double *r, double *z,
                      void *stream);
 
+/* ---- many right-hand sides and contact (Sec. 6.2) ---------------------
+ * Contact through Lagrange multipliers solves, besides the free motion, a
+ * complementarity problem on the compliance matrix W = H A^{-1} H^T of the k
+ * constraint rows H, built (Sec. 7.4) from the asynchronous preconditioner
+ * and a triangular solver for many right-hand sides, and corrects the motion
+ * with one more solve of A.  H is a k x n_dofs CSR matrix on the device:
+ * h_row_ptr [k + 1], h_col [nnz_h] (DOF indices), h_val [nnz_h] FP64.
+ * Blocks of right-hand sides R and results Z are FP64, DOF-major: entry
+ * (dof, j) at [dof * k + j].
+ * The many-right-hand-side calls need a caller-owned device workspace of
+ * fe_multi_ws_bytes(k) bytes (256-byte aligned), separate from the bound
+ * one and not kept between calls. */
+
+/* Bytes of workspace for k right-hand sides (k >= 0). */
+int fe_multi_ws_bytes(fe_ctx *ctx, int32_t k, int64_t *bytes);
+
+/* Z = P^{-1} R for k right-hand sides at once with the installed factor:
+ * the same forward / diagonal / backward sweeps as fe_precond_apply, each
+ * panel block multiplying a block of up to 128 right-hand sides on the
+ * matrix cores (arithmetic in the context's precision: FP32 for
+ * FE_PREC_MIXED, FP64 otherwise).  R, Z device [n_dofs * k].
+ * Errors: FE_ESTATE (no factor installed), FE_ENOMEM (work too small),
+ * FE_EINVAL. */
+int fe_precond_apply_multi(fe_ctx *ctx, const double *R, double *Z, int32_t k, void *work,
+                           int64_t work_bytes, void *stream);
+
+/* Compliance matrix W = H P^{-1} H^T (device [k * k], row-major FP64) with
+ * the installed factor P (Sec. 6.2, Sec. 7.4).  If Z is not NULL it
+ * receives P^{-1} H^T (device [n_dofs * k], DOF-major).  Synchronises
+ * `stream`.  Errors: FE_EINVAL (a row range of H outside [0, nnz_h] or a
+ * column outside [0, n_dofs): such entries are skipped, W is not valid),
+ * FE_ESTATE, FE_ENOMEM. */
+int fe_compliance(fe_ctx *ctx, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                  const double *h_val, int64_t nnz_h, double *W, double *Z, void *work,
+                  int64_t work_bytes, void *stream);
+
+/* y = s_h op(H) x + s_y y_in with op(H) = H (transpose = 0: x device
+ * [n_dofs], y and y_in device [k]) or H^T (transpose = 1: x device [k], y
+ * and y_in device [n_dofs]); y_in NULL counts as zero and may alias y.
+ * Gives the complementarity right-hand side H x_free - delta and the
+ * corrected load b - H^T lambda of the motion correction (Sec. 6.2).
+ * Synchronises `stream`.  Errors: FE_EINVAL (bad index, as fe_compliance). */
+int fe_constraint_apply(fe_ctx *ctx, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                        const double *h_val, int64_t nnz_h, int32_t transpose, double s_h,
+                        const double *x, double s_y, const double *y_in, double *y,
+                        void *stream);
+
+/* Projected Gauss-Seidel (Sec. 6.2) on the complementarity problem
+ *   lambda >= 0,  W lambda - c >= 0,  lambda . (W lambda - c) = 0
+ * with W device [k * k] row-major and c device [k]: each sweep visits the
+ * constraints in order and sets
+ *   lambda_i <- max(0, lambda_i - ((W lambda)_i - c_i) / W_ii)
+ * (a row with W_ii <= 0 keeps its value).  lam (device [k]) holds the start
+ * on entry and the result on exit.  Stops after max_sweeps sweeps or after
+ * the first sweep whose largest change is <= tol * max(lambda).  info
+ * (device [2], NULL allowed) receives the sweeps done and that last change.
+ * One wavefront on the GPU; k <= 4096.  Queued on `stream`.
+ * Errors: FE_EINVAL. */
+int fe_pgs(fe_ctx *ctx, int32_t k, const double *W, const double *c, double *lam,
+           int32_t max_sweeps, double tol, double *info, void *stream);
+
 /* Host-only check of the factorisation (no GPU): factor the FP64 CSR values
  * A_host (host [nnz]) with the context's ordering and supernodes, then apply
  * z = P^{-1} r on the host with the same explicit-inverse panels and the same
@@ -274,8 +335,11 @@ int fe_set_graphs(fe_ctx *ctx, int32_t enable);
 /* Per-kernel timing: when enabled, the library brackets every launch of the
  * triangular-solve and SpMV kernels with HIP events on the launch stream and
  * accumulates their durations; fe_kernel_times reads and resets them.
- *   names: 0 spmv, 1 trisolve forward, 2 trisolve backward, 3 element
- *   out_ms[k], out_count[k], out_bytes[k] (algorithmic bytes moved). */
+ *   names: 0 spmv, 1 trisolve forward, 2 trisolve backward, 3 element,
+ *          4 many-right-hand-side forward, 5 many-right-hand-side backward
+ *   out_ms[k], out_count[k], out_bytes[k]: algorithmic bytes moved for
+ *   kinds 0-3, algorithmic flops (2 per lower panel entry and right-hand
+ *   side) for kinds 4-5. */
 int fe_set_kernel_timing(fe_ctx *ctx, int32_t enable);
 int fe_kernel_times(fe_ctx *ctx, double *out_ms, int64_t *out_count, double *out_bytes,
                     int32_t n);

@@ -99,6 +99,13 @@ SIGNATURES = {
     "fe_spmv": (C.c_int, [_P, _P, _P, _P, _P]),
     "fe_precond_apply": (C.c_int, [_P, _P, _P, _P, _P]),
     "fe_host_factor_apply": (C.c_int, [_P, _P, _P, _P, C.c_int32]),
+    "fe_multi_ws_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64)]),
+    "fe_precond_apply_multi": (C.c_int, [_P, _P, _P, C.c_int32, _P, C.c_int64, _P]),
+    "fe_compliance": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64,
+                                _P]),
+    "fe_constraint_apply": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, C.c_int32,
+                                      C.c_double, _P, C.c_double, _P, _P, _P]),
+    "fe_pgs": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, C.c_double, _P, _P]),
     "fe_set_graphs": (C.c_int, [_P, C.c_int32]),
     "fe_set_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "fe_kernel_times": (C.c_int, [_P, _P, _P, _P, C.c_int32]),

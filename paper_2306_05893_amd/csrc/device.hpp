@@ -90,6 +90,37 @@ void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnD
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
                     const PcgState *state, int tile_rows);
 
+// Many right-hand sides: DOF-major n x ld blocks (ld = k rounded up to the
+// tile width bn, 64 or 128), w/y in the factor's precision, z FP64.
+template <typename T>
+void launch_multi_prep(hipStream_t st, int64_t n, int k, int ld, const double *R, T *w, T *y,
+                       double *z, const uint8_t *dof_fixed);
+template <typename T>
+void launch_multi_zero(hipStream_t st, int64_t total, T *w, T *y, double *z);
+void launch_multi_out(hipStream_t st, int64_t n, int k, int ld, const double *z, double *Z);
+template <typename T>
+void launch_multi_fwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
+                      const SnDev *sn, const int32_t *rows, const T *panels, T *w, T *y, int ld);
+template <typename T>
+void launch_multi_bwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
+                      const SnDev *sn, const int32_t *rows, const T *panels, const T *dinv,
+                      const T *y, double *z, int ld);
+// Contact: right-hand sides H^T (w, and z on fixed DOFs; blocks zeroed
+// before), W = H Z, y = s_h op(H) x + s_y y_in, projected Gauss-Seidel.  Invalid
+// row ranges or column indices of H are skipped and set *err.
+template <typename T>
+void launch_h_scatter(hipStream_t st, int kc, int64_t n, int64_t nnz_h, const int32_t *hrp,
+                      const int32_t *hcol, const double *hval, int ld, T *w, double *z,
+                      const uint8_t *dof_fixed, int *err);
+void launch_hz(hipStream_t st, int kc, int64_t n, int64_t nnz_h, const int32_t *hrp,
+               const int32_t *hcol, const double *hval, int ld, const double *z, double *W);
+void launch_h_apply(hipStream_t st, int kc, int64_t n, int64_t nnz_h, const int32_t *hrp,
+                    const int32_t *hcol, const double *hval, bool transpose, double s_h,
+                    const double *x, double s_y, const double *y_in, double *y, int *err);
+int pgs_max_constraints();
+void launch_pgs(hipStream_t st, int kc, const double *W, const double *c, double *lam,
+                int max_sweeps, double tol, double *info);
+
 // Jacobi: dinv_A[i] = 1 / A_ii ; z = dinv_A * r
 template <typename T>
 void launch_diag_inv(hipStream_t st, int64_t n, const int32_t *row_ptr, const int32_t *col,

@@ -87,6 +87,8 @@ struct fe_ctx {
   double *d_X = nullptr;
   SnDev *d_sn = nullptr;
   TileDev *d_ftiles = nullptr, *d_btiles = nullptr;
+  MTile *d_mftiles = nullptr, *d_mbtiles = nullptr;  // many-right-hand-side sweeps
+  int *d_herr = nullptr;                             // constraint-matrix index error flag
   void *d_panels[2] = {nullptr, nullptr}, *d_dinv[2] = {nullptr, nullptr};
   double *d_jdinv = nullptr;
   double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_tmp = nullptr;
@@ -141,8 +143,10 @@ struct fe_ctx {
   bool timing = false;
   std::vector<Timing> tq;
   std::vector<hipEvent_t> ev_pool;
-  double t_ms[4] = {0, 0, 0, 0}, t_bytes[4] = {0, 0, 0, 0};
-  int64_t t_count[4] = {0, 0, 0, 0};
+  static constexpr int kTimedKinds = 6;
+  double t_ms[kTimedKinds] = {}, t_bytes[kTimedKinds] = {};
+  int64_t t_count[kTimedKinds] = {};
+  int *h_flag = nullptr;  // pinned host word for error flags read back
   std::vector<double> fwd_level_bytes, bwd_level_bytes;
 
   int fail(int code, const char *fmt, ...) {
@@ -179,7 +183,8 @@ enum {
   L_PAN0, L_PAN1, L_DINV0, L_DINV1, L_JDINV, L_R, L_Z, L_P, L_Q, L_TMP, L_B, L_ACC, L_ABAR,
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
-  L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF
+  L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF,
+  L_MFT, L_MBT, L_HERR
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -237,6 +242,9 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(cg ? (int64_t)P.blk_src.size() * 4 : 0);
   L.add(cg ? (int64_t)P.n_elems * nen * nen * 9 * ts : 0);
   L.add(cg ? (int64_t)P.n_elems * nen * 3 * 8 : 0);
+  L.add((int64_t)S.mfwd_tiles.size() * (int64_t)sizeof(MTile));
+  L.add((int64_t)S.mbwd_tiles.size() * (int64_t)sizeof(MTile));
+  L.add(256);
   return L;
 }
 
@@ -395,6 +403,73 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
     launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s,
                       S.bwd_rows);
   }
+}
+
+// Workspace of the many-right-hand-side calls: an error word, then the
+// DOF-major n x ld blocks w, y (factor precision) and z (FP64).
+struct MultiWs {
+  int bn = 64, ld = 0;
+  int64_t off_w = 0, off_y = 0, off_z = 0, total = 0;
+};
+
+MultiWs multi_ws(const fe_ctx *c, int k) {
+  MultiWs m;
+  m.bn = k <= 64 ? 64 : 128;
+  m.ld = (k + m.bn - 1) / m.bn * m.bn;
+  const int64_t n = c->P.n;
+  auto r256 = [](int64_t b) { return (b + 255) / 256 * 256; };
+  m.off_w = 0;
+  m.off_y = r256(n * m.ld * (int64_t)c->tsize);
+  m.off_z = m.off_y + r256(n * m.ld * (int64_t)c->tsize);
+  m.total = m.off_z + r256(n * m.ld * 8);
+  return m;
+}
+
+// Z = P^{-1} R for the prepared blocks: level-ordered forward tiles, then
+// backward tiles (the same dependency levels as the single sweeps).
+template <typename T>
+void multi_sweeps(fe_ctx *c, const MultiWs &m, int k, T *w, T *y, double *z, hipStream_t st) {
+  const int slot = c->active_slot;
+  const T *pan = (const T *)c->d_panels[slot];
+  const T *dinv = (const T *)c->d_dinv[slot];
+  const Symbolic &S = c->S;
+  const int nkb = m.ld / m.bn;
+  for (int L = 0; L < S.n_levels; ++L) {
+    const int b = S.mfwd_level_ptr[L], e = S.mfwd_level_ptr[L + 1];
+    TimedLaunch tl(c, st, 4, 2.0 * S.level_lower[L] * k);
+    launch_multi_fwd<T>(st, c->d_mftiles + b, e - b, nkb, m.bn, c->d_sn, c->d_rows, pan, w, y,
+                        m.ld);
+  }
+  for (int L = 0; L < S.n_levels; ++L) {
+    const int b = S.mbwd_level_ptr[L], e = S.mbwd_level_ptr[L + 1];
+    TimedLaunch tl(c, st, 5, 2.0 * S.level_lower[S.n_levels - 1 - L] * k);
+    launch_multi_bwd<T>(st, c->d_mbtiles + b, e - b, nkb, m.bn, c->d_sn, c->d_rows, pan, dinv,
+                        y, z, m.ld);
+  }
+}
+
+template <typename T>
+void precond_multi(fe_ctx *c, const MultiWs &m, const double *R, double *Z, int k, char *work,
+                   hipStream_t st) {
+  T *w = (T *)(work + m.off_w), *y = (T *)(work + m.off_y);
+  double *z = (double *)(work + m.off_z);
+  launch_multi_prep<T>(st, c->P.n, k, m.ld, R, w, y, z, c->d_dof_fixed);
+  multi_sweeps<T>(c, m, k, w, y, z, st);
+  launch_multi_out(st, c->P.n, k, m.ld, z, Z);
+}
+
+template <typename T>
+void compliance(fe_ctx *c, const MultiWs &m, int k, const int32_t *hrp, const int32_t *hcol,
+                const double *hval, int64_t nnz_h, double *W, double *Z, char *work,
+                hipStream_t st) {
+  const int64_t n = c->P.n;
+  T *w = (T *)(work + m.off_w), *y = (T *)(work + m.off_y);
+  double *z = (double *)(work + m.off_z);
+  launch_multi_zero<T>(st, n * m.ld, w, y, z);
+  launch_h_scatter<T>(st, k, n, nnz_h, hrp, hcol, hval, m.ld, w, z, c->d_dof_fixed, c->d_herr);
+  multi_sweeps<T>(c, m, k, w, y, z, st);
+  launch_hz(st, k, n, nnz_h, hrp, hcol, hval, m.ld, z, W);
+  if (Z) launch_multi_out(st, n, k, m.ld, z, Z);
 }
 
 template <typename T>
@@ -844,6 +919,7 @@ fe_ctx::~fe_ctx() {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     if (copy_stream) (void)hipStreamSynchronize(copy_stream);
     if (h_state) (void)hipHostFree(h_state);
+    if (h_flag) (void)hipHostFree(h_flag);
     if (h_Asnap) (void)hipHostFree(h_Asnap);
     if (h_stage) (void)hipHostFree(h_stage);
     for (hipEvent_t e : {ev_snap_ready, ev_snap_done, ev_upload_done, ev_slot_free[0],
@@ -1028,10 +1104,14 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_part1 = ptr_at<double>(w, L, L_PART1);
   c->d_part2 = ptr_at<double>(w, L, L_PART2);
   c->d_state = ptr_at<PcgState>(w, L, L_STATE);
+  c->d_mftiles = ptr_at<MTile>(w, L, L_MFT);
+  c->d_mbtiles = ptr_at<MTile>(w, L, L_MBT);
+  c->d_herr = ptr_at<int>(w, L, L_HERR);
 
   // host-side resources
   HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
   memset(c->h_state, 0, sizeof(PcgState));
+  HIP_TRY(hipHostMalloc((void **)&c->h_flag, 256, hipHostMallocDefault));
   if (!c->gpu_factor) {
     // snapshot of A and staging of the factor: host-thread factorisation only
     HIP_TRY(hipHostMalloc(&c->h_Asnap, std::max<size_t>(1, c->P.col_idx.size() * c->tsize),
@@ -1083,6 +1163,8 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
     bt[i] = TileDev{S.bwd_tiles[i].s, S.bwd_tiles[i].r0, S.bwd_tiles[i].c0, 0};
   HIP_TRY(up(c->d_ftiles, ft.data(), ft.size() * sizeof(TileDev)));
   HIP_TRY(up(c->d_btiles, bt.data(), bt.size() * sizeof(TileDev)));
+  HIP_TRY(up(c->d_mftiles, S.mfwd_tiles.data(), S.mfwd_tiles.size() * sizeof(MTile)));
+  HIP_TRY(up(c->d_mbtiles, S.mbwd_tiles.data(), S.mbwd_tiles.size() * sizeof(MTile)));
   HIP_TRY(up(c->d_state, c->h_state, sizeof(PcgState)));
   HIP_TRY(hipStreamSynchronize(st));
 
@@ -1284,6 +1366,99 @@ int fe_precond_apply(fe_ctx *c, const void *A_vals, const double *r, double *z, 
   return FE_OK;
 }
 
+int fe_multi_ws_bytes(fe_ctx *c, int32_t k, int64_t *bytes) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (k < 0 || !bytes) return c->fail(FE_EINVAL, "bad argument");
+  *bytes = multi_ws(c, k).total;
+  return FE_OK;
+}
+
+// shared checks of the many-right-hand-side calls
+static int multi_check(fe_ctx *c, int32_t k, void *work, int64_t work_bytes) {
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (c->active_slot < 0) return c->fail(FE_ESTATE, "no factor installed");
+  if (k < 0) return c->fail(FE_EINVAL, "negative number of right-hand sides");
+  if (k == 0) return FE_OK;
+  if (!work || ((uintptr_t)work & 255)) return c->fail(FE_EINVAL, "work must be 256-byte aligned");
+  const int64_t need = multi_ws(c, k).total;
+  if (work_bytes < need)
+    return c->fail(FE_ENOMEM, "workspace too small: %lld bytes needed", (long long)need);
+  return FE_OK;
+}
+
+// Read back and clear the constraint-matrix error word (synchronises st).
+static int herr_check(fe_ctx *c, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(c->h_flag, c->d_herr, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (*c->h_flag) return c->fail(FE_EINVAL, "constraint matrix: bad row range or column index");
+  return FE_OK;
+}
+
+int fe_precond_apply_multi(fe_ctx *c, const double *R, double *Z, int32_t k, void *work,
+                           int64_t work_bytes, void *stream) {
+  if (!c) return FE_EINVAL;
+  const int rc = multi_check(c, k, work, work_bytes);
+  if (rc != FE_OK || k == 0) return rc;
+  if (!R || !Z) return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  const MultiWs m = multi_ws(c, k);
+  if (c->prec == FE_PREC_MIXED) precond_multi<float>(c, m, R, Z, k, (char *)work, st);
+  else precond_multi<double>(c, m, R, Z, k, (char *)work, st);
+  HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
+int fe_compliance(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                  const double *h_val, int64_t nnz_h, double *W, double *Z, void *work,
+                  int64_t work_bytes, void *stream) {
+  if (!c) return FE_EINVAL;
+  const int rc = multi_check(c, k, work, work_bytes);
+  if (rc != FE_OK || k == 0) return rc;
+  if (!h_row_ptr || !W || nnz_h < 0 || (nnz_h > 0 && (!h_col || !h_val)))
+    return c->fail(FE_EINVAL, "bad constraint matrix or NULL output");
+  hipStream_t st = (hipStream_t)stream;
+  const MultiWs m = multi_ws(c, k);
+  HIP_TRY(hipMemsetAsync(c->d_herr, 0, sizeof(int), st));
+  if (c->prec == FE_PREC_MIXED)
+    compliance<float>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, (char *)work, st);
+  else
+    compliance<double>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, (char *)work, st);
+  HIP_TRY(hipGetLastError());
+  return herr_check(c, st);
+}
+
+int fe_constraint_apply(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                        const double *h_val, int64_t nnz_h, int32_t transpose, double s_h,
+                        const double *x, double s_y, const double *y_in, double *y,
+                        void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (k < 0 || nnz_h < 0) return c->fail(FE_EINVAL, "bad size");
+  if (!h_row_ptr || !x || !y || (nnz_h > 0 && (!h_col || !h_val)))
+    return c->fail(FE_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_TRY(hipMemsetAsync(c->d_herr, 0, sizeof(int), st));
+  launch_h_apply(st, k, c->P.n, nnz_h, h_row_ptr, h_col, h_val, transpose != 0, s_h, x, s_y,
+                 y_in, y, c->d_herr);
+  HIP_TRY(hipGetLastError());
+  return herr_check(c, st);
+}
+
+int fe_pgs(fe_ctx *c, int32_t k, const double *W, const double *cvec, double *lam,
+           int32_t max_sweeps, double tol, double *info, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (k < 0 || k > pgs_max_constraints() || max_sweeps < 0 || !(tol >= 0.0))
+    return c->fail(FE_EINVAL, "k must be in [0, %d], max_sweeps >= 0, tol >= 0",
+                   pgs_max_constraints());
+  if (k == 0) return FE_OK;
+  if (!W || !cvec || !lam) return c->fail(FE_EINVAL, "NULL buffer");
+  launch_pgs((hipStream_t)stream, k, W, cvec, lam, max_sweeps, tol, info);
+  HIP_TRY(hipGetLastError());
+  return FE_OK;
+}
+
 int fe_host_factor_apply(fe_ctx *c, const double *A_host, const double *r_host, double *z_host,
                          int32_t n_rhs) {
   if (!c) return FE_EINVAL;
@@ -1345,7 +1520,7 @@ int fe_set_kernel_timing(fe_ctx *c, int32_t enable) {
 int fe_kernel_times(fe_ctx *c, double *out_ms, int64_t *out_count, double *out_bytes, int32_t n) {
   if (!c) return FE_EINVAL;
   drain_timing(c);
-  for (int k = 0; k < 4 && k < n; ++k) {
+  for (int k = 0; k < fe_ctx::kTimedKinds && k < n; ++k) {
     if (out_ms) out_ms[k] = c->t_ms[k];
     if (out_count) out_count[k] = c->t_count[k];
     if (out_bytes) out_bytes[k] = c->t_bytes[k];

@@ -94,6 +94,16 @@ struct Tile {
   int32_t s, r0, c0, pad;
 };
 
+// One tile of the many-right-hand-side sweeps: supernode s, the first of the
+// 64 panel rows (forward) or own columns (backward) it produces, and the
+// range [lo, hi) of the contraction it covers (panel columns forward, panel
+// rows backward).  A long contraction is split over several tiles whose
+// results are summed with atomics.
+struct MTile {
+  int32_t s, b0, lo, hi;
+};
+constexpr int kMultiRows = 64;     // output rows (forward) / columns (backward) per tile
+
 struct Symbolic {
   int64_t n = 0;                       // DOFs (incl. fixed)
   int64_t n_free = 0;
@@ -110,6 +120,10 @@ struct Symbolic {
   std::vector<Tile> fwd_tiles, bwd_tiles;
   std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
   int32_t fwd_cols = 0, bwd_rows = 0;  // tile extents in use
+  // many-right-hand-side schedules (same level order)
+  std::vector<MTile> mfwd_tiles, mbwd_tiles;
+  std::vector<int32_t> mfwd_level_ptr, mbwd_level_ptr;
+  std::vector<double> level_lower;     // panel entries on/below the diagonal per level
 };
 
 // Tile extents shared with the device kernels.

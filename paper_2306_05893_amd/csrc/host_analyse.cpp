@@ -147,6 +147,59 @@ struct Dissector {
 
 }  // namespace
 
+// Tiles of the many-right-hand-side sweeps.  Forward: one tile per 64 panel
+// rows, contracting over the own columns that row block can touch (all nc
+// for update rows, up to the diagonal for own rows).  Backward: one tile per
+// 64 own columns, contracting over the panel rows from that column block
+// down.  A level whose tiles are too few to fill the GPU has its contractions
+// cut into pieces (multiples of the 16-wide staging chunk, at least 64 long)
+// until it has about 512 tiles.
+static void build_multi_tiles(Symbolic &S, const std::vector<std::vector<int32_t>> &by_level) {
+  constexpr int kTarget = 512, kMinChunk = 64, kStage = 16;
+  const int nl = (int)by_level.size();
+  struct Base { int32_t s, b0, lo, hi; };
+  auto emit = [&](const std::vector<Base> &base, std::vector<MTile> &out) {
+    int64_t longest = 0;
+    for (const Base &b : base) longest = std::max<int64_t>(longest, b.hi - b.lo);
+    int64_t chunk = std::max<int64_t>(longest, kMinChunk);
+    auto count = [&](int64_t ch) {
+      int64_t k = 0;
+      for (const Base &b : base) k += (b.hi - b.lo + ch - 1) / ch;
+      return k;
+    };
+    while (count(chunk) < kTarget && chunk > kMinChunk)
+      chunk = std::max<int64_t>(kMinChunk, (chunk / 2 + kStage - 1) / kStage * kStage);
+    for (const Base &b : base)
+      for (int64_t lo = b.lo; lo < b.hi; lo += chunk)
+        out.push_back({b.s, b.b0, (int32_t)lo, (int32_t)std::min<int64_t>(b.hi, lo + chunk)});
+  };
+  S.mfwd_tiles.clear();
+  S.mbwd_tiles.clear();
+  S.mfwd_level_ptr.assign(1, 0);
+  S.mbwd_level_ptr.assign(1, 0);
+  S.level_lower.assign(nl, 0.0);
+  for (int L = 0; L < nl; ++L) {
+    std::vector<Base> base;
+    for (int32_t s : by_level[L]) {
+      const Supernode &sn = S.sn[s];
+      S.level_lower[L] += (double)sn.m * sn.nc - 0.5 * (double)sn.nc * (sn.nc - 1);
+      for (int32_t r0 = 0; r0 < sn.m; r0 += kMultiRows)
+        base.push_back({s, r0, 0, r0 < sn.nc ? std::min(sn.nc, r0 + kMultiRows) : sn.nc});
+    }
+    emit(base, S.mfwd_tiles);
+    S.mfwd_level_ptr.push_back((int32_t)S.mfwd_tiles.size());
+  }
+  for (int L = nl - 1; L >= 0; --L) {
+    std::vector<Base> base;
+    for (int32_t s : by_level[L]) {
+      const Supernode &sn = S.sn[s];
+      for (int32_t j0 = 0; j0 < sn.nc; j0 += kMultiRows) base.push_back({s, j0, j0, sn.m});
+    }
+    emit(base, S.mbwd_tiles);
+    S.mbwd_level_ptr.push_back((int32_t)S.mbwd_tiles.size());
+  }
+}
+
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
                     int32_t bwd_rows, Symbolic &S) {
   if (leaf_nodes <= 0) leaf_nodes = 48;
@@ -332,6 +385,7 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
   }
   S.fwd_cols = fwd_cols;
   S.bwd_rows = bwd_rows;
+  build_multi_tiles(S, by_level);
   return "";
 }
 

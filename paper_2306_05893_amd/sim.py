@@ -74,6 +74,30 @@ class Params:
         return q
 
 
+@dataclass
+class Constraints:
+    """k x n_dofs constraint matrix H in CSR form on the device (int32 row
+    pointers and columns, FP64 values)."""
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def k(self):
+        return int(self.row_ptr.numel()) - 1
+
+    @property
+    def nnz(self):
+        return int(self.col.numel())
+
+    @staticmethod
+    def from_host(H, device="cuda"):
+        rp, col, val = H
+        return Constraints(torch.as_tensor(np.ascontiguousarray(rp, np.int32), device=device),
+                           torch.as_tensor(np.ascontiguousarray(col, np.int32), device=device),
+                           torch.as_tensor(np.ascontiguousarray(val, np.float64), device=device))
+
+
 class FEContext:
     """One library context bound to a caller-owned torch workspace."""
 
@@ -101,6 +125,7 @@ class FEContext:
         self.device = torch.device(device)
         self.sizes = self.query(self.prec)
         self.ws = None
+        self._mwork = None
         self.bound = False
 
     # ---- lifetime -------------------------------------------------------
@@ -289,6 +314,105 @@ class FEContext:
         self._chk(self.lib.fe_precond_apply(self.h, _ptr(A), _ptr(r), _ptr(z), _stream()))
         return z
 
+    # ---- many right-hand sides and contact (Sec. 6.2)
+    def _multi_work(self, k):
+        b = C.c_int64()
+        self._chk(self.lib.fe_multi_ws_bytes(self.h, int(k), C.byref(b)))
+        need = max(int(b.value), 256)
+        if self._mwork is None or self._mwork.numel() < need:
+            self._mwork = None
+            self._mwork = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._mwork
+
+    def _block(self, t, name, k):
+        n = self.sizes.n_dofs
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != (n, k):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape ({n}, {k})")
+        return t
+
+    def precond_apply_multi(self, R, Z=None):
+        """Z = P^{-1} R for the k columns of R (n_dofs x k, DOF-major)."""
+        self.bind()
+        k = int(R.shape[1]) if R.dim() == 2 else -1
+        self._block(R, "R", k)
+        Z = self._block(torch.empty_like(R) if Z is None else Z, "Z", k)
+        wk = self._multi_work(k)
+        self._chk(self.lib.fe_precond_apply_multi(self.h, _ptr(R), _ptr(Z), k, _ptr(wk),
+                                                  wk.numel(), _stream()))
+        return Z
+
+    def compliance(self, H: "Constraints", want_Z=False, W=None, Z=None):
+        """W = H P^{-1} H^T (k x k) with the installed factor; also
+        Z = P^{-1} H^T (n_dofs x k) when want_Z."""
+        self.bind()
+        k = H.k
+        W = torch.empty(k, k, dtype=torch.float64, device=self.device) if W is None else W
+        if want_Z and Z is None:
+            Z = torch.empty(self.sizes.n_dofs, k, dtype=torch.float64, device=self.device)
+        if not (W.is_cuda and W.dtype == torch.float64 and W.is_contiguous()
+                and W.numel() == k * k):
+            raise ValueError("W must be a contiguous float64 CUDA tensor of k x k entries")
+        if Z is not None:
+            self._block(Z, "Z", k)
+        wk = self._multi_work(k)
+        self._chk(self.lib.fe_compliance(self.h, k, _ptr(H.row_ptr), _ptr(H.col), _ptr(H.val),
+                                         H.nnz, _ptr(W), _ptr(Z), _ptr(wk), wk.numel(),
+                                         _stream()))
+        return (W, Z) if want_Z else W
+
+    def constraint_apply(self, H: "Constraints", x, transpose=False, s_h=1.0, y_in=None,
+                         s_y=1.0, y=None):
+        """y = s_h op(H) x + s_y y_in with op(H) = H or H^T."""
+        self.bind()
+        n = self.sizes.n_dofs
+        nx, ny = (H.k, n) if transpose else (n, H.k)
+        self._vec(x, "x", nx)
+        if y_in is not None:
+            self._vec(y_in, "y_in", ny)
+        y = self._vec(torch.empty(ny, dtype=torch.float64, device=self.device) if y is None
+                      else y, "y", ny)
+        self._chk(self.lib.fe_constraint_apply(self.h, H.k, _ptr(H.row_ptr), _ptr(H.col),
+                                               _ptr(H.val), H.nnz, 1 if transpose else 0,
+                                               float(s_h), _ptr(x), float(s_y), _ptr(y_in),
+                                               _ptr(y), _stream()))
+        return y
+
+    def pgs(self, W, c, lam=None, max_sweeps=100, tol=0.0):
+        """Projected Gauss-Seidel on lambda >= 0, W lambda - c >= 0,
+        complementary.  Returns (lambda, info) with info = [sweeps, last
+        largest change] (device tensors)."""
+        self.bind()
+        k = int(c.numel())
+        self._vec(c, "c", k)
+        if not (W.is_cuda and W.dtype == torch.float64 and W.is_contiguous()
+                and W.numel() == k * k):
+            raise ValueError("W must be a contiguous float64 CUDA tensor of k x k entries")
+        lam = torch.zeros(k, dtype=torch.float64, device=self.device) if lam is None else lam
+        self._vec(lam, "lam", k)
+        info = torch.zeros(2, dtype=torch.float64, device=self.device)
+        self._chk(self.lib.fe_pgs(self.h, k, _ptr(W), _ptr(c), _ptr(lam), int(max_sweeps),
+                                  float(tol), _ptr(info), _stream()))
+        return lam, info
+
+    def contact_solve(self, A, b, H: "Constraints", delta, W=None, sweeps=200, pgs_tol=0.0,
+                      rel_tol=1e-8, max_it=1000):
+        """The three stages of Sec. 6.2 for A x = b under H x <= delta:
+        free motion A x_free = b; lambda from projected Gauss-Seidel on the
+        compliance W = H P^{-1} H^T (built from the installed factor when W
+        is None) with c = H x_free - delta; motion correction
+        x = A^{-1} (b - H^T lambda), started from x_free.
+        Returns (x, x_free, lambda, W, stats)."""
+        x_free, st_free = self.pcg_solve(A, b, rel_tol=rel_tol, max_it=max_it)
+        if W is None:
+            W = self.compliance(H)
+        c = self.constraint_apply(H, x_free, s_h=1.0, y_in=delta, s_y=-1.0)
+        lam, info = self.pgs(W, c, max_sweeps=sweeps, tol=pgs_tol)
+        rhs = self.constraint_apply(H, lam, transpose=True, s_h=-1.0, y_in=b, s_y=1.0)
+        x, st_corr = self.pcg_solve(A, rhs, x=x_free.clone(), rel_tol=rel_tol, max_it=max_it)
+        return x, x_free, lam, W, {"free": st_free, "correction": st_corr, "pgs": info}
+
     def set_graphs(self, on=True):
         self._chk(self.lib.fe_set_graphs(self.h, 1 if on else 0))
 
@@ -296,11 +420,13 @@ class FEContext:
         self._chk(self.lib.fe_set_kernel_timing(self.h, 1 if on else 0))
 
     def kernel_times(self):
-        ms = (C.c_double * 4)()
-        cnt = (C.c_int64 * 4)()
-        by = (C.c_double * 4)()
-        self._chk(self.lib.fe_kernel_times(self.h, ms, cnt, by, 4))
-        names = ["spmv", "trisolve_fwd", "trisolve_bwd", "element"]
+        """Accumulated event times per kernel family since the last call;
+        "bytes" holds algorithmic bytes, or flops for the multi_* kinds."""
+        ms = (C.c_double * 6)()
+        cnt = (C.c_int64 * 6)()
+        by = (C.c_double * 6)()
+        self._chk(self.lib.fe_kernel_times(self.h, ms, cnt, by, 6))
+        names = ["spmv", "trisolve_fwd", "trisolve_bwd", "element", "multi_fwd", "multi_bwd"]
         return {n: {"ms": ms[i], "count": cnt[i], "bytes": by[i]} for i, n in enumerate(names)}
 
     def reset(self):

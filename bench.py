@@ -185,6 +185,112 @@ def _other_workloads():
     return out
 
 
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def _contact(k=246, n_rep=10, pgs_sweeps=100):
+    """Contact through Lagrange multipliers on the hex beam (paper Sec. 6.2;
+    its liver scene averages 246 constraints per step): the compliance matrix
+    W = H P^{-1} H^T built with the many-right-hand-side sweeps, against the
+    same W from k single-right-hand-side preconditioner applications; the
+    projected Gauss-Seidel solve; one whole three-stage contact solve.  Mixed
+    precision (FP32 MFMA sweeps) and FP64 (FP64 MFMA)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2306_05893_amd import FE_PREC_FP64, FE_PREC_MIXED
+    from paper_2306_05893_amd.sim import Constraints, Simulation
+
+    w = synth.make("hex_beam")
+    Hh, d0 = synth.contact_constraints(w, k, 31)
+    out = {"workload": f"hex_beam (107163 DOFs), {k} contact constraints on the y = min face "
+                       "(alternating node-on-plane and point-on-triangle rows)", "k": k}
+    for tag, prec in (("mixed", FE_PREC_MIXED), ("fp64", FE_PREC_FP64)):
+        sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=True)
+        ctx = sim.ctx
+        A, b = ctx.assemble(sim.params, sim.q, sim.v)
+        ctx.factorize_now(A, 0)
+        H = Constraints.from_host(Hh, "cuda")
+        W = ctx.compliance(H)                      # warm-up (workspace, code objects)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(n_rep):
+            t0 = time.perf_counter()
+            ctx.compliance(H, W=W)                 # synchronises
+            ms.append(1e3 * (time.perf_counter() - t0))
+        ms.sort()
+        # kernel-level figures of the many-right-hand-side sweeps (HIP events
+        # around every launch, separate pass)
+        ctx.set_kernel_timing(True)
+        ctx.kernel_times()
+        for _ in range(3):
+            ctx.compliance(H, W=W)
+        kt = ctx.kernel_times()
+        ctx.set_kernel_timing(False)
+        # the same W from k single applications (columns of H^T one by one)
+        HT = torch.zeros(w.n_dofs, k, dtype=torch.float64, device="cuda")
+        rp, col, val = Hh
+        for a in range(k):
+            HT[torch.as_tensor(col[rp[a]:rp[a + 1]].astype(np.int64), device="cuda"), a] = \
+                torch.as_tensor(val[rp[a]:rp[a + 1]], device="cuda")
+        cols = [HT[:, a].contiguous() for a in range(k)]
+        z = torch.empty(w.n_dofs, dtype=torch.float64, device="cuda")
+        ctx.precond_apply(cols[0], z=z)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a in range(k):
+            ctx.precond_apply(cols[a], z=z)
+        torch.cuda.synchronize()
+        single_ms = 1e3 * (time.perf_counter() - t0)
+        # projected Gauss-Seidel, fixed sweep count
+        c = ctx.constraint_apply(H, sim.q, s_h=1.0)
+        lam, info = ctx.pgs(W, c, max_sweeps=pgs_sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, info = ctx.pgs(W, c, max_sweeps=pgs_sweeps)
+        torch.cuda.synchronize()
+        pgs_ms = 1e3 * (time.perf_counter() - t0)
+        # whole contact solve: free PCG, compliance, PGS, correction PCG
+        x_free, _ = ctx.pcg_solve(A, b, rel_tol=1e-8, max_it=500)
+        hx = ctx.constraint_apply(H, x_free).cpu().numpy()
+        delta = torch.as_tensor(hx - np.abs(hx).max() * 0.5 * d0, device="cuda")
+        ctx.contact_solve(A, b, H, delta, sweeps=pgs_sweeps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, _, lam, _, st = ctx.contact_solve(A, b, H, delta, sweeps=pgs_sweeps)
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t0)
+        dt = "f32" if prec == FE_PREC_MIXED else "f64"
+        kern = {}
+        for name in ("multi_fwd", "multi_bwd"):
+            d = kt[name]
+            tf = d["bytes"] / (d["ms"] * 1e-3) / 1e12
+            kern[name] = {"launches": d["count"], "avg_us": round(1e3 * d["ms"] / d["count"], 2),
+                          "TFLOPs": round(tf, 2),
+                          "frac_mfma_peak": round(tf / MFMA_PEAK_TFLOPS[dt], 4)}
+        tot_ms = kt["multi_fwd"]["ms"] + kt["multi_bwd"]["ms"]
+        tot_fl = kt["multi_fwd"]["bytes"] + kt["multi_bwd"]["bytes"]
+        out[tag] = {"compliance_ms_median": round(ms[len(ms) // 2], 3),
+                    "compliance_ms_min": round(ms[0], 3),
+                    "single_rhs_applies_ms": round(single_ms, 3),
+                    "speedup_vs_single_rhs": round(single_ms / ms[len(ms) // 2], 2),
+                    "sweeps_TFLOPs": round(tot_fl / (tot_ms * 1e-3) / 1e12, 2),
+                    "sweeps_frac_mfma_peak": round(tot_fl / (tot_ms * 1e-3) / 1e12
+                                                   / MFMA_PEAK_TFLOPS[dt], 4),
+                    "mfma_dtype": dt, "kernels": kern,
+                    "pgs_ms": round(pgs_ms, 3), "pgs_sweeps": int(info[0]),
+                    "contact_solve_ms": round(solve_ms, 3),
+                    "contact_active": int((lam > 0).sum()),
+                    "cg_it_free_correction": [st["free"].iterations,
+                                              st["correction"].iterations]}
+        print(f"[bench] contact {tag}: W in {out[tag]['compliance_ms_median']} ms "
+              f"({out[tag]['speedup_vs_single_rhs']}x vs single applies), sweeps "
+              f"{out[tag]['sweeps_TFLOPs']} TFLOP/s", file=sys.stderr, flush=True)
+        ctx.close()
+    return out
+
+
 def _factor_only(n=5):
     """Standalone GPU refactorisations of the hex beam (mixed precision, FP64
     factor), timed one by one: the input of the factorisation kernel profile."""
@@ -262,6 +368,8 @@ def main():
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--factor-only", type=int, default=0, metavar="N",
                     help="only time N standalone GPU refactorisations of the hex beam")
+    ap.add_argument("--contact-only", action="store_true",
+                    help="only run the contact measurements (compliance matrix, PGS)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
@@ -271,6 +379,9 @@ def main():
         return
     if args.factor_only > 0:
         _factor_only(args.factor_only)
+        return
+    if args.contact_only:
+        print(json.dumps({"contact": _contact()}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -326,6 +437,7 @@ def main():
         adj_rate, adj_ok = _adjoint_rate(w, FE_PREC_MIXED)
         print(f"[bench] adjoint {adj_rate:.1f} steps/s", file=sys.stderr, flush=True)
         others = _other_workloads()
+        contact = _contact()
         extras = {"warm_start_steps_per_s": round(warm["steps_per_s"], 3),
                   "warm_start_cg_it_mean": round(warm["cg_it_mean"], 2),
                   "host_factor_steps_per_s": round(host["steps_per_s"], 3),
@@ -335,7 +447,7 @@ def main():
                   "fp64_ms_per_step": round(fp64["ms_per_step"], 4),
                   "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
                   "adjoint_steps_per_s": round(adj_rate, 3), "adjoint_finite": adj_ok,
-                  "other_workloads": others}
+                  "other_workloads": others, "contact": contact}
 
     # per-kernel figures from HIP events recorded around every launch
     kern = {}

@@ -100,11 +100,17 @@ void launch_multi_zero(hipStream_t st, int64_t total, T *w, T *y, double *z);
 void launch_multi_out(hipStream_t st, int64_t n, int k, int ld, const double *z, double *Z);
 template <typename T>
 void launch_multi_fwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
-                      const SnDev *sn, const int32_t *rows, const T *panels, T *w, T *y, int ld);
+                      const SnDev *sn, const int32_t *rows, const T *panels, T *w, T *y, int ld,
+                      int k);
 template <typename T>
 void launch_multi_bwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
-                      const SnDev *sn, const int32_t *rows, const T *panels, const T *dinv,
-                      const T *y, double *z, int ld);
+                      const SnDev *sn, const int32_t *rows, const T *panels, const T *dinv, T *y,
+                      double *z, int ld, int k);
+// After each backward level: y <- -z on that level's DOFs (the inputs the
+// lower levels read).
+template <typename T>
+void launch_multi_conv(hipStream_t st, const int32_t *dofs, int64_t cnt, int ld, const double *z,
+                       T *y);
 // Contact: right-hand sides H^T (w, and z on fixed DOFs; blocks zeroed
 // before), W = H Z, y = s_h op(H) x + s_y y_in, projected Gauss-Seidel.  Invalid
 // row ranges or column indices of H are skipped and set *err.

@@ -88,6 +88,7 @@ struct fe_ctx {
   SnDev *d_sn = nullptr;
   TileDev *d_ftiles = nullptr, *d_btiles = nullptr;
   MTile *d_mftiles = nullptr, *d_mbtiles = nullptr;  // many-right-hand-side sweeps
+  int32_t *d_mbdofs = nullptr;                       // own DOFs per backward level
   int *d_herr = nullptr;                             // constraint-matrix index error flag
   void *d_panels[2] = {nullptr, nullptr}, *d_dinv[2] = {nullptr, nullptr};
   double *d_jdinv = nullptr;
@@ -184,7 +185,7 @@ enum {
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
   L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF,
-  L_MFT, L_MBT, L_HERR
+  L_MFT, L_MBT, L_HERR, L_MBDOF
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -245,6 +246,7 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add((int64_t)S.mfwd_tiles.size() * (int64_t)sizeof(MTile));
   L.add((int64_t)S.mbwd_tiles.size() * (int64_t)sizeof(MTile));
   L.add(256);
+  L.add((int64_t)S.mbwd_dofs.size() * 4);
   return L;
 }
 
@@ -438,13 +440,19 @@ void multi_sweeps(fe_ctx *c, const MultiWs &m, int k, T *w, T *y, double *z, hip
     const int b = S.mfwd_level_ptr[L], e = S.mfwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 4, 2.0 * S.level_lower[L] * k);
     launch_multi_fwd<T>(st, c->d_mftiles + b, e - b, nkb, m.bn, c->d_sn, c->d_rows, pan, w, y,
-                        m.ld);
+                        m.ld, k);
   }
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.mbwd_level_ptr[L], e = S.mbwd_level_ptr[L + 1];
-    TimedLaunch tl(c, st, 5, 2.0 * S.level_lower[S.n_levels - 1 - L] * k);
-    launch_multi_bwd<T>(st, c->d_mbtiles + b, e - b, nkb, m.bn, c->d_sn, c->d_rows, pan, dinv,
-                        y, z, m.ld);
+    {
+      TimedLaunch tl(c, st, 5, 2.0 * S.level_lower[S.n_levels - 1 - L] * k);
+      launch_multi_bwd<T>(st, c->d_mbtiles + b, e - b, nkb, m.bn, c->d_sn, c->d_rows, pan, dinv,
+                          y, z, m.ld, k);
+    }
+    if (L + 1 < S.n_levels) {
+      const int32_t d0 = S.mbwd_dof_ptr[L], d1 = S.mbwd_dof_ptr[L + 1];
+      launch_multi_conv<T>(st, c->d_mbdofs + d0, d1 - d0, m.ld, z, y);
+    }
   }
 }
 
@@ -1107,6 +1115,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_mftiles = ptr_at<MTile>(w, L, L_MFT);
   c->d_mbtiles = ptr_at<MTile>(w, L, L_MBT);
   c->d_herr = ptr_at<int>(w, L, L_HERR);
+  c->d_mbdofs = ptr_at<int32_t>(w, L, L_MBDOF);
 
   // host-side resources
   HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
@@ -1165,6 +1174,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   HIP_TRY(up(c->d_btiles, bt.data(), bt.size() * sizeof(TileDev)));
   HIP_TRY(up(c->d_mftiles, S.mfwd_tiles.data(), S.mfwd_tiles.size() * sizeof(MTile)));
   HIP_TRY(up(c->d_mbtiles, S.mbwd_tiles.data(), S.mbwd_tiles.size() * sizeof(MTile)));
+  HIP_TRY(up(c->d_mbdofs, S.mbwd_dofs.data(), S.mbwd_dofs.size() * 4));
   HIP_TRY(up(c->d_state, c->h_state, sizeof(PcgState)));
   HIP_TRY(hipStreamSynchronize(st));
 

@@ -124,6 +124,7 @@ struct Symbolic {
   std::vector<MTile> mfwd_tiles, mbwd_tiles;
   std::vector<int32_t> mfwd_level_ptr, mbwd_level_ptr;
   std::vector<double> level_lower;     // panel entries on/below the diagonal per level
+  std::vector<int32_t> mbwd_dofs, mbwd_dof_ptr;  // own DOFs per backward level
 };
 
 // Tile extents shared with the device kernels.

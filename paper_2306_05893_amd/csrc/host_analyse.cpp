@@ -155,7 +155,7 @@ struct Dissector {
 // cut into pieces (multiples of the 16-wide staging chunk, at least 64 long)
 // until it has about 512 tiles.
 static void build_multi_tiles(Symbolic &S, const std::vector<std::vector<int32_t>> &by_level) {
-  constexpr int kTarget = 512, kMinChunk = 64, kStage = 16;
+  constexpr int kTarget = 256, kMinChunk = 128, kStage = 32;
   const int nl = (int)by_level.size();
   struct Base { int32_t s, b0, lo, hi; };
   auto emit = [&](const std::vector<Base> &base, std::vector<MTile> &out) {
@@ -189,14 +189,18 @@ static void build_multi_tiles(Symbolic &S, const std::vector<std::vector<int32_t
     emit(base, S.mfwd_tiles);
     S.mfwd_level_ptr.push_back((int32_t)S.mfwd_tiles.size());
   }
+  S.mbwd_dofs.clear();
+  S.mbwd_dof_ptr.assign(1, 0);
   for (int L = nl - 1; L >= 0; --L) {
     std::vector<Base> base;
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
       for (int32_t j0 = 0; j0 < sn.nc; j0 += kMultiRows) base.push_back({s, j0, j0, sn.m});
+      for (int32_t j = 0; j < sn.nc; ++j) S.mbwd_dofs.push_back(S.rows[sn.rows_off + j]);
     }
     emit(base, S.mbwd_tiles);
     S.mbwd_level_ptr.push_back((int32_t)S.mbwd_tiles.size());
+    S.mbwd_dof_ptr.push_back((int32_t)S.mbwd_dofs.size());
   }
 }
 

@@ -43,7 +43,7 @@ struct Mma<double> {
 };
 
 constexpr int kMR = kMultiRows;  // output rows (forward) / columns (backward) per tile
-constexpr int kKC = 16;          // contraction chunk staged in LDS
+constexpr int kKC = 32;          // contraction chunk staged in LDS
 constexpr int kPad = 16;         // LDS row padding: the four 16-lane groups of
                                  // a fragment read hit different banks
 
@@ -69,8 +69,8 @@ __device__ inline void load_row(const T *src, T (&v)[BV]) {
   }
 }
 
-// One staged chunk: four MFMA k-steps over the 16 entries of the chunk.  The
-// wave owns rows wr..wr+31 and columns wc..wc+BN/2-1 of the block's result.
+// One staged chunk: kKC / 4 MFMA k-steps.  The wave owns rows wr..wr+31 and
+// columns wc..wc+BN/2-1 of the block's result.
 template <typename T, int BN>
 __device__ inline void mma_chunk(const T (*sA)[kMR + kPad], const T (*sB)[BN + kPad], int wr,
                                  int wc, int lane, typename Mma<T>::acc (&acc)[2][BN / 32]) {
@@ -90,156 +90,157 @@ __device__ inline void mma_chunk(const T (*sA)[kMR + kPad], const T (*sB)[BN + k
   }
 }
 
-// Forward tile: T = G[r0:r0+64, lo:hi] * w[rows[lo:hi], k0:k0+BN] for
-// supernode s; own rows (i < nc) add T into y, update rows subtract it from
-// w (their DOFs belong to ancestors, finished at a later level).  Entries of
-// L11^{-1} above its diagonal are read as zero.  blockIdx.y picks the
-// right-hand-side block.  The global loads of the next chunk are issued
-// before the MFMAs of the current one.
-template <typename T, int BN>
-__global__ __launch_bounds__(256) void k_mfwd(const MTile *__restrict__ tiles,
-                                              const SnDev *__restrict__ sn,
-                                              const int32_t *__restrict__ rows,
-                                              const T *__restrict__ panels, T *w, T *y, int ld) {
-  constexpr int NCB = BN / 32, BV = BN / 16;
-  __shared__ T sA[kKC][kMR + kPad];  // sA[k][i] = G[r0 + i][c + k]
-  __shared__ T sB[kKC][BN + kPad];   // sB[k][j] = w[rows[c + k]][k0 + j]
-  const MTile t = tiles[blockIdx.x];
+// Work units are (tile, right-hand-side block) pairs, the block index
+// fastest.  The hardware hands workgroup b of a launch to XCD b % 8; a launch
+// has 8 * per workgroups and workgroup b takes unit (b % 8) * per + b / 8,
+// so every XCD runs a contiguous range of units: the row blocks of one
+// supernode (which gather the same inputs) and the right-hand-side blocks of
+// one tile (which read the same panel entries) meet in the same L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_unit(int per) {
+  const int b = (int)blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+
+// One sweep tile, forward (FWD) or backward.
+//   forward:  T = G[r0:r0+64, lo:hi] * src[rows[lo:hi], k0:k0+BN]; own rows
+//             (i < nc) add T into y, update rows subtract it from src = w
+//             (their DOFs belong to ancestors, finished at a later level);
+//   backward: x = G[lo:hi, j0:j0+64]^T v added into z for the own columns,
+//             v = dinv src on the own rows and src on the update rows, with
+//             src = y holding y on the own rows and -z on the update rows
+//             (ancestor DOFs, final before this level).
+// A tile that covers its whole contraction writes its own-row results with
+// plain stores (no other tile writes them); split tiles and the update rows
+// of the forward sweep add with atomics.  Padding columns (>= kreal) are not
+// written.
+// Entries of L11^{-1} above its diagonal read as zero.  Staging: every global
+// load is unconditional with its index clamped into the tile, the masks are
+// applied when the values go to LDS, and the gather index of the next chunk
+// is loaded one chunk ahead, so no load waits behind a branch or a dependent
+// index load and the loads of chunk c + 1 are in flight during the MFMAs of
+// chunk c.
+template <typename T, int BN, bool FWD>
+__global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles, int n_units,
+                                                int n_kb, int per, const SnDev *__restrict__ sn,
+                                                const int32_t *__restrict__ rows,
+                                                const T *__restrict__ panels,
+                                                const T *__restrict__ dinv, T *src, T *y,
+                                                double *z, int ld, int kreal) {
+  constexpr int NCB = BN / 32, BV = BN / 8;
+  __shared__ T sA[kKC][kMR + kPad];  // forward: G[r0 + i][c + k]; backward: G[c + k][j0 + j]
+  __shared__ T sB[kKC][BN + kPad];   // src[rows[c + k]][k0 + j]
+  const int u = xcd_unit(per);
+  if (u >= n_units) return;
+  const MTile t = tiles[u / n_kb];
   const SnDev d = sn[t.s];
   const int32_t *rw = rows + d.rows_off;
-  const int m = d.m, nc = d.nc, r0 = t.b0;
-  const int64_t k0 = (int64_t)blockIdx.y * BN;
+  const int m = d.m, nc = d.nc, b0 = t.b0, hi = t.hi;
+  const int64_t k0 = (int64_t)(u % n_kb) * BN;
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv & 1) * 32, wc = (wv >> 1) * (BN / 2);
   const T *G = panels + d.panel_off;
-  const int ak = tid >> 4, ai = (tid & 15) * 4;  // staging: panel column, 4 rows
-  const int bk = tid >> 4, bj = (tid & 15) * BV; // staging: input row, BV values
-  T ra[4], rb[BV];
-  auto load = [&](int c) {
-    const int j = c + ak;
+  // staging roles.  A, forward: panel column ak of the chunk, 8 rows from
+  // ai; backward: own column aj, 8 panel rows from ak.  B: input row bk of
+  // the chunk, BV values from bj.
+  const int fa_k = tid >> 3, fa_i = (tid & 7) * 8;
+  const int ba_j = tid >> 2, ba_k = (tid & 3) * 8;
+  const int bk = tid >> 3, bj = (tid & 7) * BV;
+  const T *Gb = G + (int64_t)min(b0 + ba_j, nc - 1) * m;  // backward: this thread's column
+  T ra[8], rb[BV], sc = T(1);
+  unsigned amask = 0;
+  bool bok = false;
+  auto load = [&](int c, int32_t dof) {
+    amask = 0;
+    if constexpr (FWD) {
+      const int j = c + fa_k, jc = min(j, hi - 1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = r0 + ai + q;
-      const bool ok = i < m && j < t.hi && (i >= nc || j <= i);
-      ra[q] = ok ? G[(int64_t)j * m + i] : T(0);
-    }
-    const int jb = c + bk;
-    if (jb < t.hi) {
-      load_row<T, BV>(w + (int64_t)rw[jb] * ld + k0 + bj, rb);
+      for (int q = 0; q < 8; ++q) {
+        const int i = b0 + fa_i + q;
+        ra[q] = G[(int64_t)jc * m + min(i, m - 1)];
+        amask |= (i < m && j < hi && (i >= nc || j <= i)) ? (1u << q) : 0u;
+      }
     } else {
+      const int j = b0 + ba_j;
 #pragma unroll
-      for (int v = 0; v < BV; ++v) rb[v] = T(0);
+      for (int q = 0; q < 8; ++q) {
+        const int i = c + ba_k + q;
+        ra[q] = Gb[min(i, hi - 1)];
+        amask |= (i < hi && j < nc && (i >= nc || i >= j)) ? (1u << q) : 0u;
+      }
     }
+    bok = c + bk < hi;
+    if constexpr (!FWD) {
+      const T di = dinv[dof];
+      sc = c + bk < nc ? di : T(1);
+    }
+    load_row<T, BV>(src + (int64_t)dof * ld + k0 + bj, rb);
   };
   typename Mma<T>::acc acc[2][NCB];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[r][c] = typename Mma<T>::acc{0, 0, 0, 0};
-  load(t.lo);
-  for (int c = t.lo; c < t.hi; c += kKC) {
+  load(t.lo, rw[min(t.lo + bk, hi - 1)]);
+  int32_t gnext = rw[min(t.lo + kKC + bk, hi - 1)];
+  for (int c = t.lo; c < hi; c += kKC) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sA[ak][ai + q] = ra[q];
+    for (int q = 0; q < 8; ++q) {
+      const T v = (amask >> q) & 1u ? ra[q] : T(0);
+      if constexpr (FWD) sA[fa_k][fa_i + q] = v;
+      else sA[ba_k + q][ba_j] = v;
+    }
 #pragma unroll
-    for (int v = 0; v < BV; ++v) sB[bk][bj + v] = rb[v];
+    for (int v = 0; v < BV; ++v) {
+      if constexpr (FWD) sB[bk][bj + v] = bok ? rb[v] : T(0);
+      else sB[bk][bj + v] = bok ? sc * rb[v] : T(0);
+    }
     __syncthreads();
-    if (c + kKC < t.hi) load(c + kKC);
+    if (c + kKC < hi) {
+      load(c + kKC, gnext);
+      gnext = rw[min(c + 2 * kKC + bk, hi - 1)];
+    }
     mma_chunk<T, BN>(sA, sB, wr, wc, lane, acc);
   }
+  // whole contraction in this tile: forward [0, min(nc, r0 + 64)) for a
+  // block with own rows, backward [j0, m)
+  const bool whole = FWD ? (t.lo == 0 && hi == (b0 < nc ? min(nc, b0 + kMR) : nc))
+                         : (t.lo == b0 && hi == m);
+  const int col0 = (int)k0 + wc + (lane & 15);
 #pragma unroll
   for (int r = 0; r < 2; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = r0 + wr + 16 * r + Mma<T>::row(lane, q);
-      if (i >= m) continue;
-      const int64_t o = (int64_t)rw[i] * ld + k0 + wc + (lane & 15);
+      const int i = b0 + wr + 16 * r + Mma<T>::row(lane, q);
+      if (i >= (FWD ? m : nc)) continue;
+      const int64_t o = (int64_t)rw[i] * ld + col0;
 #pragma unroll
       for (int c = 0; c < NCB; ++c) {
+        if (col0 + 16 * c >= kreal) continue;
         const T v = acc[r][c][q];
-        if (i < nc) atomicAdd(y + o + 16 * c, v);
-        else atomicAdd(w + o + 16 * c, -v);
+        if constexpr (FWD) {
+          if (i >= nc) atomicAdd(src + o + 16 * c, -v);
+          else if (whole) y[o + 16 * c] = v;
+          else atomicAdd(y + o + 16 * c, v);
+        } else {
+          if (whole) z[o + 16 * c] = (double)v;
+          else atomicAdd(z + o + 16 * c, (double)v);
+        }
       }
     }
 }
 
-// Backward tile: x[rows[j0:j0+64], k0:k0+BN] += G[lo:hi, j0:j0+64]^T v with
-// v_i = dinv y (own rows, i < nc) or -z (update rows: ancestor DOFs, final
-// before this level).  Entries of L11^{-1} above its diagonal read as zero.
-template <typename T, int BN>
-__global__ __launch_bounds__(256) void k_mbwd(const MTile *__restrict__ tiles,
-                                              const SnDev *__restrict__ sn,
-                                              const int32_t *__restrict__ rows,
-                                              const T *__restrict__ panels,
-                                              const T *__restrict__ dinv,
-                                              const T *__restrict__ y, double *z, int ld) {
-  constexpr int NCB = BN / 32, BV = BN / 16;
-  __shared__ T sA[kKC][kMR + kPad];  // sA[k][j] = G[c + k][j0 + j]
-  __shared__ T sB[kKC][BN + kPad];   // sB[k][j] = v[c + k][k0 + j]
-  const MTile t = tiles[blockIdx.x];
-  const SnDev d = sn[t.s];
-  const int32_t *rw = rows + d.rows_off;
-  const int m = d.m, nc = d.nc, j0 = t.b0;
-  const int64_t k0 = (int64_t)blockIdx.y * BN;
-  const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wr = (wv & 1) * 32, wc = (wv >> 1) * (BN / 2);
-  const T *G = panels + d.panel_off;
-  const int aj = tid >> 2, ak = (tid & 3) * 4;   // staging: own column, 4 panel rows
-  const int bk = tid >> 4, bj = (tid & 15) * BV; // staging: input row, BV values
-  T ra[4], rb[BV];
-  auto load = [&](int c) {
-    const int j = j0 + aj;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = c + ak + q;
-      const bool ok = i < t.hi && j < nc && (i >= nc || i >= j);
-      ra[q] = ok ? G[(int64_t)j * m + i] : T(0);
-    }
-    const int ib = c + bk;
-    if (ib < t.hi) {
-      const int64_t dof = rw[ib];
-      if (ib < nc) {
-        const T s = dinv[dof];
-        load_row<T, BV>(y + dof * ld + k0 + bj, rb);
-#pragma unroll
-        for (int v = 0; v < BV; ++v) rb[v] *= s;
-      } else {
-        double zz[BV];
-        load_row<double, BV>(z + dof * ld + k0 + bj, zz);
-#pragma unroll
-        for (int v = 0; v < BV; ++v) rb[v] = (T)(-zz[v]);
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < BV; ++v) rb[v] = T(0);
-    }
-  };
-  typename Mma<T>::acc acc[2][NCB];
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int c = 0; c < NCB; ++c) acc[r][c] = typename Mma<T>::acc{0, 0, 0, 0};
-  load(t.lo);
-  for (int c = t.lo; c < t.hi; c += kKC) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) sA[ak + q][aj] = ra[q];
-#pragma unroll
-    for (int v = 0; v < BV; ++v) sB[bk][bj + v] = rb[v];
-    __syncthreads();
-    if (c + kKC < t.hi) load(c + kKC);
-    mma_chunk<T, BN>(sA, sB, wr, wc, lane, acc);
-  }
-#pragma unroll
-  for (int r = 0; r < 2; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = j0 + wr + 16 * r + Mma<T>::row(lane, q);
-      if (j >= nc) continue;
-      const int64_t o = (int64_t)rw[j] * ld + k0 + wc + (lane & 15);
-#pragma unroll
-      for (int c = 0; c < NCB; ++c) atomicAdd(z + o + 16 * c, (double)acc[r][c][q]);
-    }
+// y <- -z on the DOFs of one backward level once they are final: later
+// (lower) levels read them as update-row inputs.
+template <typename T>
+__global__ void k_mconv(const int32_t *__restrict__ dofs, int64_t cnt, int ld,
+                        const double *__restrict__ z, T *y) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= cnt * ld) return;
+  const int64_t e = idx / ld;
+  const int64_t o = (int64_t)dofs[e] * ld + (idx - e * ld);
+  y[o] = (T)(-z[o]);
 }
 
 // w = r, y = 0, z = r on fixed DOFs (their rows of A are the identity) and 0
@@ -372,75 +373,110 @@ __global__ void k_htx(int kc, int64_t n, int64_t nnz_h, const int32_t *__restric
   }
 }
 
-__device__ inline double wave_sum64(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// ---------------------------------------------------- projected Gauss-Seidel
+// Lane-crossing helpers on the two 32-bit halves of a double.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Projected Gauss-Seidel on lambda >= 0, W lambda - c >= 0, complementary:
-// one wavefront; lambda lives in LDS, each lane holds NR entries of the
-// current row of W and has the next row's loads in flight while the current
-// row is reduced.  The butterfly sum leaves the same total in every lane, so
-// all lanes take the same update and the same exit decision.  A sweep whose
-// largest change is <= tol * max(lambda) ends the iteration.  A row whose
-// diagonal is not positive leaves its multiplier unchanged.
-template <int NR>
+__device__ inline double readlane_d(double v, int l) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)x, l);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the wavefront, the same value in every lane: within each row of 16
+// lanes pairwise exchanges (lane ^ 1, lane ^ 2, then the mirrors that pair
+// the two quads of each half and the two halves of the row), each pairing two
+// lanes that then hold the same sum; then the four row sums read as scalars.
+__device__ inline double wave_total(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+// Projected Gauss-Seidel on lambda >= 0, W lambda - c >= 0, complementary,
+// by one wavefront.  lambda, c and the diagonal of W live in LDS (lane l
+// reads the entries l + 64 q of lambda for its part of a row product; the
+// scalars of row i are broadcast reads).  The rows of W stream through a ring
+// of D register buffers, each refilled with the row D positions ahead
+// (wrapping into the next sweep) as soon as it has been used, so D rows of
+// loads are in flight while a row is reduced.  Every lane computes the same
+// update and lane 0 stores it; within one wavefront LDS accesses complete in
+// order, so the next row reads it (the wave barriers keep the compiler from
+// moving LDS accesses across the store).  A sweep whose largest change is
+// <= tol * max(lambda) ends the iteration.  A row whose diagonal is not
+// positive keeps its multiplier.
+template <int NR, int D>
 __global__ __launch_bounds__(64) void k_pgs(int kc, const double *__restrict__ W,
                                             const double *__restrict__ c, double *lam,
                                             int max_sweeps, double tol, double *info) {
-  __shared__ double s_lam[64 * NR];
+  __shared__ double s_lam[64 * NR], s_c[64 * NR], s_dg[64 * NR];
   const int lane = (int)threadIdx.x;
+  for (int j = lane; j < 64 * NR; j += 64) {
+    const bool ok = j < kc;
+    s_lam[j] = ok ? lam[j] : 0.0;
+    s_c[j] = ok ? c[j] : 0.0;
+    s_dg[j] = ok ? W[(int64_t)j * kc + j] : 0.0;
+  }
+  double buf[D][NR];
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const int j = lane + 64 * q;
-    s_lam[j] = j < kc ? lam[j] : 0.0;
+  for (int d = 0; d < D; ++d) {
+    const int64_t r = (int64_t)(d % kc) * kc;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) buf[d][q] = W[r + min(lane + 64 * q, kc - 1)];
   }
   __syncthreads();
-  double wr[NR];
+  int row = 0, sweeps = 0;
+  double dmax = 0.0, lmax = 0.0, last = 0.0;
+  bool done = max_sweeps <= 0;
+  // rows run in groups of D with no branch around the loads (a group may run
+  // past the end of the last sweep: those rows are computed but not stored),
+  // so the wait for each ring slot counts only the loads issued before it
+  while (!done) {
 #pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const int j = lane + 64 * q;
-    wr[q] = j < kc ? W[j] : 0.0;
-  }
-  int sweeps = 0;
-  double dmax = 0.0;
-  while (sweeps < max_sweeps) {
-    dmax = 0.0;
-    double lmax = 0.0;
-    for (int i = 0; i < kc; ++i) {
-      const int64_t nxt = (int64_t)(i + 1 < kc ? i + 1 : 0) * kc;
-      double wn[NR];
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const int j = lane + 64 * q;
-        wn[q] = j < kc ? W[nxt + j] : 0.0;
-      }
+    for (int d = 0; d < D; ++d) {
+      const double li = s_lam[row], ci = s_c[row], wii = s_dg[row];
       double p = 0.0;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) p += wr[q] * s_lam[lane + 64 * q];
-      p = wave_sum64(p);
-      const double li = s_lam[i];
-      const double wii = W[(int64_t)i * kc + i];
-      const double nl = wii > 0.0 ? fmax(0.0, li - (p - c[i]) / wii) : li;
+      for (int q = 0; q < NR; ++q) p += buf[d][q] * s_lam[lane + 64 * q];
+      p = wave_total(p);
+      const double nl = wii > 0.0 ? fmax(0.0, li - (p - ci) / wii) : li;
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0 && !done) s_lam[row] = nl;
+      __builtin_amdgcn_wave_barrier();
       dmax = fmax(dmax, fabs(nl - li));
       lmax = fmax(lmax, nl);
-      __syncthreads();
-      if (lane == 0) s_lam[i] = nl;
-      __syncthreads();
+      // unconditional loads, clamped to the row: the entries of lanes past
+      // the end meet lambda = 0 in the product, so they need no masking (a
+      // select here would wait for the load at once)
+      const int64_t nr = (int64_t)((row + D) % kc) * kc;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) wr[q] = wn[q];
+      for (int q = 0; q < NR; ++q) buf[d][q] = W[nr + min(lane + 64 * q, kc - 1)];
+      if (++row == kc) {
+        row = 0;
+        if (!done) {
+          ++sweeps;
+          last = dmax;
+          done = sweeps >= max_sweeps || dmax <= tol * lmax;
+        }
+        dmax = 0.0;
+        lmax = 0.0;
+      }
     }
-    ++sweeps;
-    if (dmax <= tol * lmax) break;
   }
-#pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    const int j = lane + 64 * q;
-    if (j < kc) lam[j] = s_lam[j];
-  }
+  __syncthreads();
+  for (int j = lane; j < kc; j += 64) lam[j] = s_lam[j];
   if (lane == 0 && info) {
     info[0] = (double)sweeps;
-    info[1] = dmax;
+    info[1] = last;
   }
 }
 
@@ -465,21 +501,38 @@ void launch_multi_out(hipStream_t st, int64_t n, int k, int ld, const double *z,
 
 template <typename T>
 void launch_multi_fwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
-                      const SnDev *sn, const int32_t *rows, const T *panels, T *w, T *y, int ld) {
+                      const SnDev *sn, const int32_t *rows, const T *panels, T *w, T *y, int ld,
+                      int k) {
   if (n_tiles <= 0 || n_kb <= 0) return;
-  const dim3 grid((unsigned)n_tiles, (unsigned)n_kb);
-  if (bn == 128) k_mfwd<T, 128><<<grid, 256, 0, st>>>(tiles, sn, rows, panels, w, y, ld);
-  else k_mfwd<T, 64><<<grid, 256, 0, st>>>(tiles, sn, rows, panels, w, y, ld);
+  const int units = n_tiles * n_kb, per = (units + kXcds - 1) / kXcds;
+  const unsigned grid = (unsigned)(per * kXcds);
+  if (bn == 128)
+    k_msweep<T, 128, true><<<grid, 256, 0, st>>>(tiles, units, n_kb, per, sn, rows, panels,
+                                                  nullptr, w, y, nullptr, ld, k);
+  else
+    k_msweep<T, 64, true><<<grid, 256, 0, st>>>(tiles, units, n_kb, per, sn, rows, panels,
+                                                 nullptr, w, y, nullptr, ld, k);
 }
 
 template <typename T>
 void launch_multi_bwd(hipStream_t st, const MTile *tiles, int n_tiles, int n_kb, int bn,
-                      const SnDev *sn, const int32_t *rows, const T *panels, const T *dinv,
-                      const T *y, double *z, int ld) {
+                      const SnDev *sn, const int32_t *rows, const T *panels, const T *dinv, T *y,
+                      double *z, int ld, int k) {
   if (n_tiles <= 0 || n_kb <= 0) return;
-  const dim3 grid((unsigned)n_tiles, (unsigned)n_kb);
-  if (bn == 128) k_mbwd<T, 128><<<grid, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, ld);
-  else k_mbwd<T, 64><<<grid, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, ld);
+  const int units = n_tiles * n_kb, per = (units + kXcds - 1) / kXcds;
+  const unsigned grid = (unsigned)(per * kXcds);
+  if (bn == 128)
+    k_msweep<T, 128, false><<<grid, 256, 0, st>>>(tiles, units, n_kb, per, sn, rows, panels,
+                                                   dinv, y, nullptr, z, ld, k);
+  else
+    k_msweep<T, 64, false><<<grid, 256, 0, st>>>(tiles, units, n_kb, per, sn, rows, panels,
+                                                  dinv, y, nullptr, z, ld, k);
+}
+
+template <typename T>
+void launch_multi_conv(hipStream_t st, const int32_t *dofs, int64_t cnt, int ld, const double *z,
+                       T *y) {
+  if (cnt * ld > 0) k_mconv<T><<<grid_for(cnt * ld), 256, 0, st>>>(dofs, cnt, ld, z, y);
 }
 
 template <typename T>
@@ -512,13 +565,14 @@ int pgs_max_constraints() { return 64 * 64; }
 
 void launch_pgs(hipStream_t st, int kc, const double *W, const double *c, double *lam,
                 int max_sweeps, double tol, double *info) {
-  if (kc <= 64) k_pgs<1><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else if (kc <= 128) k_pgs<2><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else if (kc <= 256) k_pgs<4><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else if (kc <= 512) k_pgs<8><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else if (kc <= 1024) k_pgs<16><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else if (kc <= 2048) k_pgs<32><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
-  else k_pgs<64><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  // register ring depth D shrinks as the rows get longer (D * NR <= 64)
+  if (kc <= 64) k_pgs<1, 8><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else if (kc <= 128) k_pgs<2, 8><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else if (kc <= 256) k_pgs<4, 8><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else if (kc <= 512) k_pgs<8, 8><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else if (kc <= 1024) k_pgs<16, 4><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else if (kc <= 2048) k_pgs<32, 2><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
+  else k_pgs<64, 1><<<1, 64, 0, st>>>(kc, W, c, lam, max_sweeps, tol, info);
 }
 
 #define FE_INST(T)                                                                             \
@@ -526,10 +580,12 @@ void launch_pgs(hipStream_t st, int kc, const double *W, const double *c, double
                                      double *, const uint8_t *);                               \
   template void launch_multi_zero<T>(hipStream_t, int64_t, T *, T *, double *);                \
   template void launch_multi_fwd<T>(hipStream_t, const MTile *, int, int, int, const SnDev *,  \
-                                    const int32_t *, const T *, T *, T *, int);                \
+                                    const int32_t *, const T *, T *, T *, int, int);           \
   template void launch_multi_bwd<T>(hipStream_t, const MTile *, int, int, int, const SnDev *,  \
-                                    const int32_t *, const T *, const T *, const T *,          \
-                                    double *, int);                                            \
+                                    const int32_t *, const T *, const T *, T *, double *, int, \
+                                    int);                                                      \
+  template void launch_multi_conv<T>(hipStream_t, const int32_t *, int64_t, int,               \
+                                     const double *, T *);                                     \
   template void launch_h_scatter<T>(hipStream_t, int, int64_t, int64_t, const int32_t *,       \
                                     const int32_t *, const double *, int, T *, double *,       \
                                     const uint8_t *, int *);

@@ -43,7 +43,10 @@ struct Mma<double> {
 };
 
 constexpr int kMR = kMultiRows;  // output rows (forward) / columns (backward) per tile
-constexpr int kKC = 32;          // contraction chunk staged in LDS
+// contraction chunk staged in LDS: 32 for FP32; 16 for FP64, whose larger
+// registers and LDS tiles would otherwise leave too few waves per SIMD
+template <typename T>
+constexpr int chunk_of() { return sizeof(T) == 8 ? 16 : 32; }
 constexpr int kPad = 16;         // LDS row padding: the four 16-lane groups of
                                  // a fragment read hit different banks
 
@@ -69,15 +72,15 @@ __device__ inline void load_row(const T *src, T (&v)[BV]) {
   }
 }
 
-// One staged chunk: kKC / 4 MFMA k-steps.  The wave owns rows wr..wr+31 and
+// One staged chunk: KC / 4 MFMA k-steps.  The wave owns rows wr..wr+31 and
 // columns wc..wc+BN/2-1 of the block's result.
-template <typename T, int BN>
+template <typename T, int BN, int KC>
 __device__ inline void mma_chunk(const T (*sA)[kMR + kPad], const T (*sB)[BN + kPad], int wr,
                                  int wc, int lane, typename Mma<T>::acc (&acc)[2][BN / 32]) {
   constexpr int NCB = BN / 32;
   const int kk = lane >> 4, ii = lane & 15;
 #pragma unroll
-  for (int kq = 0; kq < kKC; kq += 4) {
+  for (int kq = 0; kq < KC; kq += 4) {
     T a[2], b[NCB];
 #pragma unroll
     for (int r = 0; r < 2; ++r) a[r] = sA[kq + kk][wr + 16 * r + ii];
@@ -127,9 +130,13 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
                                                 const T *__restrict__ panels,
                                                 const T *__restrict__ dinv, T *src, T *y,
                                                 double *z, int ld, int kreal) {
-  constexpr int NCB = BN / 32, BV = BN / 8;
-  __shared__ T sA[kKC][kMR + kPad];  // forward: G[r0 + i][c + k]; backward: G[c + k][j0 + j]
-  __shared__ T sB[kKC][BN + kPad];   // src[rows[c + k]][k0 + j]
+  constexpr int KC = chunk_of<T>();
+  constexpr int NA = KC / 4;          // panel values staged per thread
+  constexpr int TPC = kMR / NA;       // forward: threads per staged panel column
+  constexpr int TPR = 256 / KC;       // threads per staged input row
+  constexpr int NCB = BN / 32, BV = BN / TPR;
+  __shared__ T sA[KC][kMR + kPad];  // forward: G[r0 + i][c + k]; backward: G[c + k][j0 + j]
+  __shared__ T sB[KC][BN + kPad];   // src[rows[c + k]][k0 + j]
   const int u = xcd_unit(per);
   if (u >= n_units) return;
   const MTile t = tiles[u / n_kb];
@@ -140,14 +147,14 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
   const int tid = (int)threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wr = (wv & 1) * 32, wc = (wv >> 1) * (BN / 2);
   const T *G = panels + d.panel_off;
-  // staging roles.  A, forward: panel column ak of the chunk, 8 rows from
-  // ai; backward: own column aj, 8 panel rows from ak.  B: input row bk of
-  // the chunk, BV values from bj.
-  const int fa_k = tid >> 3, fa_i = (tid & 7) * 8;
-  const int ba_j = tid >> 2, ba_k = (tid & 3) * 8;
-  const int bk = tid >> 3, bj = (tid & 7) * BV;
+  // staging roles.  A, forward: panel column fa_k of the chunk, NA rows from
+  // fa_i; backward: own column ba_j, NA panel rows from ba_k.  B: input row
+  // bk of the chunk, BV values from bj.
+  const int fa_k = tid / TPC, fa_i = (tid % TPC) * NA;
+  const int ba_j = tid >> 2, ba_k = (tid & 3) * NA;
+  const int bk = tid / TPR, bj = (tid % TPR) * BV;
   const T *Gb = G + (int64_t)min(b0 + ba_j, nc - 1) * m;  // backward: this thread's column
-  T ra[8], rb[BV], sc = T(1);
+  T ra[NA], rb[BV], sc = T(1);
   unsigned amask = 0;
   bool bok = false;
   auto load = [&](int c, int32_t dof) {
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
     if constexpr (FWD) {
       const int j = c + fa_k, jc = min(j, hi - 1);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < NA; ++q) {
         const int i = b0 + fa_i + q;
         ra[q] = G[(int64_t)jc * m + min(i, m - 1)];
         amask |= (i < m && j < hi && (i >= nc || j <= i)) ? (1u << q) : 0u;
@@ -163,7 +170,7 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
     } else {
       const int j = b0 + ba_j;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < NA; ++q) {
         const int i = c + ba_k + q;
         ra[q] = Gb[min(i, hi - 1)];
         amask |= (i < hi && j < nc && (i >= nc || i >= j)) ? (1u << q) : 0u;
@@ -182,11 +189,11 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
 #pragma unroll
     for (int c = 0; c < NCB; ++c) acc[r][c] = typename Mma<T>::acc{0, 0, 0, 0};
   load(t.lo, rw[min(t.lo + bk, hi - 1)]);
-  int32_t gnext = rw[min(t.lo + kKC + bk, hi - 1)];
-  for (int c = t.lo; c < hi; c += kKC) {
+  int32_t gnext = rw[min(t.lo + KC + bk, hi - 1)];
+  for (int c = t.lo; c < hi; c += KC) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < NA; ++q) {
       const T v = (amask >> q) & 1u ? ra[q] : T(0);
       if constexpr (FWD) sA[fa_k][fa_i + q] = v;
       else sA[ba_k + q][ba_j] = v;
@@ -197,11 +204,11 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
       else sB[bk][bj + v] = bok ? sc * rb[v] : T(0);
     }
     __syncthreads();
-    if (c + kKC < hi) {
-      load(c + kKC, gnext);
-      gnext = rw[min(c + 2 * kKC + bk, hi - 1)];
+    if (c + KC < hi) {
+      load(c + KC, gnext);
+      gnext = rw[min(c + 2 * KC + bk, hi - 1)];
     }
-    mma_chunk<T, BN>(sA, sB, wr, wc, lane, acc);
+    mma_chunk<T, BN, KC>(sA, sB, wr, wc, lane, acc);
   }
   // whole contraction in this tile: forward [0, min(nc, r0 + 64)) for a
   // block with own rows, backward [j0, m)
@@ -403,28 +410,37 @@ __device__ inline double wave_total(double v) {
 }
 
 // Projected Gauss-Seidel on lambda >= 0, W lambda - c >= 0, complementary,
-// by one wavefront.  lambda, c and the diagonal of W live in LDS (lane l
-// reads the entries l + 64 q of lambda for its part of a row product; the
-// scalars of row i are broadcast reads).  The rows of W stream through a ring
-// of D register buffers, each refilled with the row D positions ahead
-// (wrapping into the next sweep) as soon as it has been used, so D rows of
-// loads are in flight while a row is reduced.  Every lane computes the same
-// update and lane 0 stores it; within one wavefront LDS accesses complete in
-// order, so the next row reads it (the wave barriers keep the compiler from
-// moving LDS accesses across the store).  A sweep whose largest change is
-// <= tol * max(lambda) ends the iteration.  A row whose diagonal is not
-// positive keeps its multiplier.
+// by one wavefront.  Lane l holds the multipliers l + 64 q (q < NR) in
+// registers; c, 1 / W_ii and W_{i,i-1} are broadcast reads from LDS.  The rows
+// of W stream through a ring of D register buffers, each refilled with the
+// row D positions ahead (wrapping into the next sweep) as soon as it has been
+// used.  Row products are computed one row ahead: while row i is updated,
+// the product of row i + 1 with the multipliers as they stand before that
+// update is reduced, and the update of row i + 1 adds W_{i+1,i} times the
+// change of lambda_i.  So the reduction of one row overlaps the scalar update
+// of the previous one.  Every lane computes the same update; the owner lane
+// of lambda_i keeps it (the selects are written so that the compiler keeps
+// the multipliers in registers).  A sweep whose largest change is <= tol *
+// max(lambda) ends the iteration.  A row whose diagonal is not positive keeps
+// its multiplier.
 template <int NR, int D>
 __global__ __launch_bounds__(64) void k_pgs(int kc, const double *__restrict__ W,
                                             const double *__restrict__ c, double *lam,
                                             int max_sweeps, double tol, double *info) {
-  __shared__ double s_lam[64 * NR], s_c[64 * NR], s_dg[64 * NR];
+  __shared__ double s_c[64 * NR], s_inv[64 * NR], s_sub[64 * NR];
   const int lane = (int)threadIdx.x;
   for (int j = lane; j < 64 * NR; j += 64) {
     const bool ok = j < kc;
-    s_lam[j] = ok ? lam[j] : 0.0;
     s_c[j] = ok ? c[j] : 0.0;
-    s_dg[j] = ok ? W[(int64_t)j * kc + j] : 0.0;
+    const double wii = ok ? W[(int64_t)j * kc + j] : 0.0;
+    s_inv[j] = wii > 0.0 ? 1.0 / wii : 0.0;
+    s_sub[j] = ok ? W[(int64_t)j * kc + (j + kc - 1) % kc] : 0.0;
+  }
+  double lr[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int j = lane + 64 * q;
+    lr[q] = j < kc ? lam[j] : 0.0;
   }
   double buf[D][NR];
 #pragma unroll
@@ -434,32 +450,60 @@ __global__ __launch_bounds__(64) void k_pgs(int kc, const double *__restrict__ W
     for (int q = 0; q < NR; ++q) buf[d][q] = W[r + min(lane + 64 * q, kc - 1)];
   }
   __syncthreads();
+  // product of row 0 with the starting multipliers; slot 0 then takes row D
+  double pre = 0.0;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) pre += buf[0][q] * lr[q];
+  pre = wave_total(pre);
+  {
+    const int64_t nr = (int64_t)(D % kc) * kc;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) buf[0][q] = W[nr + min(lane + 64 * q, kc - 1)];
+  }
   int row = 0, sweeps = 0;
-  double dmax = 0.0, lmax = 0.0, last = 0.0;
+  int lrow = (D + 1) % kc;  // row the next refill loads: row + 1 + D (mod kc)
+  double dprev = 0.0, dmax = 0.0, lmax = 0.0, last = 0.0;
   bool done = max_sweeps <= 0;
   // rows run in groups of D with no branch around the loads (a group may run
-  // past the end of the last sweep: those rows are computed but not stored),
+  // past the end of the last sweep: those rows are computed but not kept),
   // so the wait for each ring slot counts only the loads issued before it
   while (!done) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const double li = s_lam[row], ci = s_c[row], wii = s_dg[row];
-      double p = 0.0;
+      const int nxt = (d + 1) % D;  // ring slot of row + 1
+      const int own = row & 63, qi = row >> 6;
+      const double ci = s_c[row], inv = s_inv[row], sub = s_sub[row];
+      double li = lr[0];
 #pragma unroll
-      for (int q = 0; q < NR; ++q) p += buf[d][q] * s_lam[lane + 64 * q];
-      p = wave_total(p);
-      const double nl = wii > 0.0 ? fmax(0.0, li - (p - ci) / wii) : li;
-      __builtin_amdgcn_wave_barrier();
-      if (lane == 0 && !done) s_lam[row] = nl;
-      __builtin_amdgcn_wave_barrier();
-      dmax = fmax(dmax, fabs(nl - li));
+      for (int q = 1; q < NR; ++q) {
+        li = q == qi ? lr[q] : li;
+        asm volatile("" : "+v"(li));
+      }
+      li = readlane_d(li, own);
+      // product of row + 1 with the multipliers before the update of row
+      double pn = 0.0;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) pn += buf[nxt][q] * lr[q];
+      const double p = pre + sub * dprev;
+      const double nl = inv > 0.0 ? fmax(0.0, li - (p - ci) * inv) : li;
+      const bool keep = lane == own && !done;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        lr[q] = keep && q == qi ? nl : lr[q];
+        asm volatile("" : "+v"(lr[q]));
+      }
+      pn = wave_total(pn);
+      dprev = nl - li;
+      dmax = fmax(dmax, fabs(dprev));
       lmax = fmax(lmax, nl);
+      pre = pn;
       // unconditional loads, clamped to the row: the entries of lanes past
       // the end meet lambda = 0 in the product, so they need no masking (a
       // select here would wait for the load at once)
-      const int64_t nr = (int64_t)((row + D) % kc) * kc;
+      const int64_t nr = (int64_t)lrow * kc;
 #pragma unroll
-      for (int q = 0; q < NR; ++q) buf[d][q] = W[nr + min(lane + 64 * q, kc - 1)];
+      for (int q = 0; q < NR; ++q) buf[nxt][q] = W[nr + min(lane + 64 * q, kc - 1)];
+      lrow = lrow + 1 == kc ? 0 : lrow + 1;
       if (++row == kc) {
         row = 0;
         if (!done) {
@@ -472,8 +516,11 @@ __global__ __launch_bounds__(64) void k_pgs(int kc, const double *__restrict__ W
       }
     }
   }
-  __syncthreads();
-  for (int j = lane; j < kc; j += 64) lam[j] = s_lam[j];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int j = lane + 64 * q;
+    if (j < kc) lam[j] = lr[q];
+  }
   if (lane == 0 && info) {
     info[0] = (double)sweeps;
     info[1] = last;

@@ -45,6 +45,9 @@ def adjoint_rollout(w, E, states, lam_qT, lam_vT, solver="dense"):
 
     Returns (dL/dE [E], dL/dq0 [n], dL/dv0 [n]).
     """
+    if w.material not in (0, 1):
+        raise ValueError("the adjoint recursion covers the neo-Hookean and St Venant-Kirchhoff "
+                         "materials (f = dPsi/dq, K its Hessian)")
     pat = pattern(w)
     fixed = w.fixed.astype(bool)
     h, al, be = w.h, w.alpha, w.beta

@@ -53,10 +53,9 @@ def element_data(w, q, E=None) -> ElementData:
     nen = w.conn.shape[1]
     Xe = w.X[w.conn]
     xe = q.reshape(-1, 3)[w.conn]
-    G, dV = elements.quadrature(w.elem_type, Xe)
-    mu, lam = elements.lame(E, w.nu)
-    f = elements.element_force(xe, G, dV, mu, lam, w.material)
-    K = elements.element_stiffness(xe, G, dV, mu, lam, w.material).reshape(-1, 3 * nen, 3 * nen)
+    f, K = elements.element_force_stiffness(w.elem_type, Xe, xe, E, w.nu, w.material,
+                                            w.mr_c01_share)
+    K = K.reshape(-1, 3 * nen, 3 * nen)
     m = elements.element_mass(w.elem_type, Xe, w.rho)
     M = np.einsum("eab,ij->eaibj", m, np.eye(3)).reshape(-1, 3 * nen, 3 * nen)
     p_grav = np.einsum("eab,j->eaj", m, w.gravity)

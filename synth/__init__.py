@@ -37,7 +37,10 @@ import numpy as np
 
 NEO_HOOKEAN = 0
 ST_VENANT_KIRCHHOFF = 1
-MATERIAL_NAMES = {NEO_HOOKEAN: "neo-hookean", ST_VENANT_KIRCHHOFF: "stvk"}
+COROTATIONAL = 2
+MOONEY_RIVLIN = 3
+MATERIAL_NAMES = {NEO_HOOKEAN: "neo-hookean", ST_VENANT_KIRCHHOFF: "stvk",
+                  COROTATIONAL: "corotational", MOONEY_RIVLIN: "mooney-rivlin"}
 
 TET4 = 4
 HEX8 = 8
@@ -164,6 +167,7 @@ class Workload:
     lag: int = 0                   # factor lag d (deterministic mode)
     dims: tuple = (0, 0, 0)        # cells per axis of the structured grid
     spacing: float = 0.01
+    mr_c01_share: float = 0.25     # Mooney-Rivlin: share of mu/2 carried by C01
     extra: dict = field(default_factory=dict)
 
     @property

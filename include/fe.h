@@ -63,8 +63,16 @@ extern "C" {
 #define FE_TET4 4               /* linear tetrahedron, 1 quadrature point    */
 #define FE_HEX8 8               /* trilinear hexahedron, 2x2x2 Gauss points  */
 
-#define FE_NEO_HOOKEAN 0        /* compressible neo-Hookean                  */
-#define FE_STVK        1        /* St Venant-Kirchhoff                       */
+#define FE_NEO_HOOKEAN   0      /* compressible neo-Hookean                  */
+#define FE_STVK          1      /* St Venant-Kirchhoff                       */
+#define FE_COROTATIONAL  2      /* co-rotational linear elasticity (Sec. 3.1,
+                                   Eq. "eqmodel"): f = R K0 (R^T x - X),
+                                   K = R K0 R^T, R the rotation of the polar
+                                   decomposition of F at the element centre  */
+#define FE_MOONEY_RIVLIN 3      /* Mooney-Rivlin in the isochoric invariants
+                                   (Sec. 3.1, MJED materials):
+                                   C10 (J^-2/3 I1 - 3) + C01 (J^-4/3 I2 - 3)
+                                   + kappa/2 (ln J)^2                         */
 
 #define FE_PREC_FP64  0
 #define FE_PREC_MIXED 1
@@ -106,11 +114,15 @@ typedef struct {
   double alpha, beta;         /* Rayleigh damping B = alpha M + beta K        */
   double rho;                 /* density                                      */
   double nu;                  /* Poisson ratio                                */
-  int32_t material;           /* FE_NEO_HOOKEAN or FE_STVK                    */
+  int32_t material;           /* FE_NEO_HOOKEAN, FE_STVK, FE_COROTATIONAL or
+                                 FE_MOONEY_RIVLIN                             */
   int32_t pad_;
   double gravity[3];          /* body acceleration                            */
   const double *E;            /* device [n_elems] Young's modulus per element */
   const double *f_nodal;      /* device [3 n_nodes] point loads, or NULL      */
+  double mr_c01_share;        /* Mooney-Rivlin: C10 = (1 - s) mu / 2,
+                                 C01 = s mu / 2, kappa = lambda + 2 mu / 3
+                                 (mu, lambda from E, nu); s in [0, 1]          */
 } fe_params;
 
 typedef struct {
@@ -234,7 +246,8 @@ int fe_pcg_solve(fe_ctx *ctx, const void *A_vals, const double *b, double *x,
 int fe_step(fe_ctx *ctx, double *q, double *v, const fe_params *params,
             const fe_step_opts *opts, double *a_out, void *stream, fe_step_stats *stats);
 
-/* One reverse step of the adjoint of fe_step (not in the paper).  Given the
+/* One reverse step of the adjoint of fe_step (not in the paper), for the
+ * neo-Hookean and St Venant-Kirchhoff materials (FE_EINVAL otherwise).  Given the
  * state (q_n, v_n) of the forward step, its output velocity v_np1 and the
  * incoming adjoints lam_q_in = dL/dq_{n+1}, lam_v_in = dL/dv_{n+1}:
  *   abar = h lam_v_in + h^2 lam_q_in (fixed DOFs 0);  A mu = abar (same PCG);

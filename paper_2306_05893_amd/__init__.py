@@ -5,10 +5,12 @@ The compute path is the HIP library ``libfe_mi355x.so`` behind the C ABI of
 does not load the library; ``FEContext`` / ``Simulation`` do, and fail loudly
 if it has not been built.
 """
-from ._lib import (FE_FACTOR_ASYNC, FE_FACTOR_DETERMINISTIC, FE_HEX8, FE_NEO_HOOKEAN,
-                   FE_PREC_FP64, FE_PREC_MIXED, FE_STVK, FE_TET4, FEError, load)
+from ._lib import (FE_COROTATIONAL, FE_FACTOR_ASYNC, FE_FACTOR_DETERMINISTIC, FE_HEX8,
+                   FE_MOONEY_RIVLIN, FE_NEO_HOOKEAN, FE_PREC_FP64, FE_PREC_MIXED, FE_STVK,
+                   FE_TET4, FEError, load)
 
-__all__ = ["FE_FACTOR_ASYNC", "FE_FACTOR_DETERMINISTIC", "FE_HEX8", "FE_NEO_HOOKEAN",
+__all__ = ["FE_COROTATIONAL", "FE_FACTOR_ASYNC", "FE_FACTOR_DETERMINISTIC", "FE_HEX8",
+           "FE_MOONEY_RIVLIN", "FE_NEO_HOOKEAN",
            "FE_PREC_FP64", "FE_PREC_MIXED", "FE_STVK", "FE_TET4", "FEError", "load",
            "FEContext", "Simulation", "Params", "StepOptions", "rollout"]
 

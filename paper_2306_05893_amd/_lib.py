@@ -30,6 +30,8 @@ FE_TET4 = 4
 FE_HEX8 = 8
 FE_NEO_HOOKEAN = 0
 FE_STVK = 1
+FE_COROTATIONAL = 2
+FE_MOONEY_RIVLIN = 3
 FE_PREC_FP64 = 0
 FE_PREC_MIXED = 1
 FE_FACTOR_DETERMINISTIC = 0
@@ -51,7 +53,7 @@ class fe_params(C.Structure):
     _fields_ = [("h", C.c_double), ("alpha", C.c_double), ("beta", C.c_double),
                 ("rho", C.c_double), ("nu", C.c_double), ("material", C.c_int32),
                 ("pad_", C.c_int32), ("gravity", C.c_double * 3), ("E", C.c_void_p),
-                ("f_nodal", C.c_void_p)]
+                ("f_nodal", C.c_void_p), ("mr_c01_share", C.c_double)]
 
 
 class fe_sizes(C.Structure):

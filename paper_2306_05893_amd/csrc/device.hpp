@@ -39,8 +39,9 @@ struct PcgState {
 struct ElemParams {
   double h, alpha, beta, rho, nu;
   double gx, gy, gz;
-  int32_t material;     // 0 neo-Hookean, 1 StVK
+  int32_t material;     // 0 neo-Hookean, 1 StVK, 2 co-rotational, 3 Mooney-Rivlin
   int32_t pad;
+  double mr_c01_share;  // Mooney-Rivlin: share of mu/2 carried by C01
 };
 
 // ---------------------------------------------------------------- launchers

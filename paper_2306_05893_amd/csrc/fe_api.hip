@@ -267,6 +267,7 @@ ElemParams to_elem(const fe_params *p) {
   e.gz = p->gravity[2];
   e.material = p->material;
   e.pad = 0;
+  e.mr_c01_share = p->mr_c01_share;
   return e;
 }
 
@@ -667,8 +668,11 @@ int assemble(fe_ctx *c, const fe_params *p, const double *q, const double *v, T 
 int check_params(fe_ctx *c, const fe_params *p) {
   if (!p) return c->fail(FE_EINVAL, "params is NULL");
   if (!p->E) return c->fail(FE_EINVAL, "params->E is NULL");
-  if (p->material != FE_NEO_HOOKEAN && p->material != FE_STVK)
+  if (p->material != FE_NEO_HOOKEAN && p->material != FE_STVK &&
+      p->material != FE_COROTATIONAL && p->material != FE_MOONEY_RIVLIN)
     return c->fail(FE_EINVAL, "unknown material %d", p->material);
+  if (p->material == FE_MOONEY_RIVLIN && !(p->mr_c01_share >= 0.0 && p->mr_c01_share <= 1.0))
+    return c->fail(FE_EINVAL, "mr_c01_share must be in [0, 1]");
   if (!(p->h > 0)) return c->fail(FE_EINVAL, "h must be positive");
   if (!(p->nu > -1.0 && p->nu < 0.5)) return c->fail(FE_EINVAL, "nu out of range");
   return FE_OK;
@@ -872,6 +876,9 @@ int adjoint_impl(fe_ctx *c, const double *q_n, const double *v_n, const double *
                  double *dE, const fe_params *p, const fe_step_opts *o, hipStream_t st,
                  fe_solve_stats *stats) {
   const int64_t n = c->P.n;
+  if (p && p->material != FE_NEO_HOOKEAN && p->material != FE_STVK)
+    return c->fail(FE_EINVAL, "the adjoint step covers the neo-Hookean and St Venant-Kirchhoff "
+                              "materials");
   T *A = (T *)c->d_A;
   // A at q_n (b is not needed but assembled alongside)
   int rc = assemble<T>(c, p, q_n, v_n, A, c->d_b, st);

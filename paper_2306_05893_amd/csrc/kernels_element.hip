@@ -318,6 +318,483 @@ __global__ __launch_bounds__(256) void k_elem_hex(
                          bvec, ebuf, rbuf);
 }
 
+// ---------------------------------------------- Mooney-Rivlin, co-rotational
+// Both are evaluated in FP64 whatever the context precision: the
+// Mooney-Rivlin stress in the isochoric invariants and the polar factor R
+// both lose every digit to cancellation in FP32 near rest (F = I + H with
+// small H); the results are rounded to T once.
+
+// Forward-mode dual number (value, derivative along one direction).
+struct Dual {
+  double v, d;
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ inline Dual operator*(double s, Dual a) { return {s * a.v, s * a.d}; }
+__device__ inline Dual operator/(Dual a, Dual b) {
+  const double r = 1.0 / b.v;
+  return {a.v * r, (a.d - a.v * r * b.d) * r};
+}
+__device__ inline Dual dlog(Dual a) { return {log(a.v), a.d / a.v}; }
+__device__ inline Dual dexp(Dual a) {
+  const double e = exp(a.v);
+  return {e, e * a.d};
+}
+
+// Mooney-Rivlin first Piola stress, decoupled compressible form
+//   Psi = C10 (J^{-2/3} I1 - 3) + C01 (J^{-4/3} I2 - 3) + kappa/2 (ln J)^2,
+//   P = 2 C10 J^{-2/3} (F - I1/3 F^{-T})
+//     + 2 C01 J^{-4/3} (I1 F - F C - 2/3 I2 F^{-T}) + kappa ln J F^{-T},
+// with dI1/dF = 2F, dI2/dF = 2(I1 F - F C), dJ/dF = J F^{-T}.
+__device__ inline void mr_piola(const Dual *F, double c10, double c01, double kappa, Dual *P) {
+  Dual C[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      C[i * 3 + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+  const Dual I1 = C[0] + C[4] + C[8];
+  Dual trCC = {0.0, 0.0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) trCC = trCC + C[i * 3 + j] * C[j * 3 + i];
+  const Dual I2 = 0.5 * (I1 * I1 - trCC);
+  // cofactors: F^{-T} = cof(F) / J
+  Dual cof[9];
+  cof[0] = F[4] * F[8] - F[5] * F[7];
+  cof[1] = F[5] * F[6] - F[3] * F[8];
+  cof[2] = F[3] * F[7] - F[4] * F[6];
+  cof[3] = F[2] * F[7] - F[1] * F[8];
+  cof[4] = F[0] * F[8] - F[2] * F[6];
+  cof[5] = F[1] * F[6] - F[0] * F[7];
+  cof[6] = F[1] * F[5] - F[2] * F[4];
+  cof[7] = F[2] * F[3] - F[0] * F[5];
+  cof[8] = F[0] * F[4] - F[1] * F[3];
+  const Dual J = F[0] * cof[0] + F[1] * cof[1] + F[2] * cof[2];
+  const Dual lnJ = dlog(J);
+  const Dual j23 = dexp((-2.0 / 3.0) * lnJ), j43 = j23 * j23;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const Dual FiT = cof[i * 3 + j] / J;
+      const Dual FC = F[i * 3] * C[j] + F[i * 3 + 1] * C[3 + j] + F[i * 3 + 2] * C[6 + j];
+      const Dual t1 = (2.0 * c10) * j23 * (F[i * 3 + j] - (1.0 / 3.0) * I1 * FiT);
+      const Dual t2 =
+          (2.0 * c01) * j43 * (I1 * F[i * 3 + j] - FC - (2.0 / 3.0) * I2 * FiT);
+      P[i * 3 + j] = t1 + t2 + kappa * lnJ * FiT;
+    }
+}
+
+// Column `dir` (F_kl, dir = 3k + l) of the elasticity tensor dP/dF and the
+// stress itself at F = I + H, all scaled by dV.  Returns J.
+__device__ inline double mr_column(const double *H, int dir, double c10, double c01, double kappa,
+                                   double dV, double *Acol, double *P) {
+  Dual F[9], Pd[9];
+  for (int m = 0; m < 9; ++m) F[m] = {H[m] + ((m == 0 || m == 4 || m == 8) ? 1.0 : 0.0),
+                                      m == dir ? 1.0 : 0.0};
+  const double J = F[0].v * (F[4].v * F[8].v - F[5].v * F[7].v) -
+                   F[1].v * (F[3].v * F[8].v - F[5].v * F[6].v) +
+                   F[2].v * (F[3].v * F[7].v - F[4].v * F[6].v);
+  if (!(J > 0.0)) return J;
+  mr_piola(F, c10, c01, kappa, Pd);
+  for (int m = 0; m < 9; ++m) {
+    Acol[m] = Pd[m].d * dV;
+    P[m] = Pd[m].v * dV;
+  }
+  return J;
+}
+
+// Rotation factor of the polar decomposition F = R U by the Newton iteration
+// R <- (R + R^{-T}) / 2 (quadratic convergence, at most 30 steps).  Returns
+// false if an iterate is singular or inverted.
+__device__ inline bool polar_rotation(const double *F, double *R) {
+  for (int m = 0; m < 9; ++m) R[m] = F[m];
+  for (int it = 0; it < 30; ++it) {
+    const double d = det3(R);
+    if (!(d > 0.0)) return false;
+    double Ri[9];
+    inv3(R, d, Ri);
+    double diff = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double rn = 0.5 * (R[i * 3 + j] + Ri[j * 3 + i]);
+        diff = fmax(diff, fabs(rn - R[i * 3 + j]));
+        R[i * 3 + j] = rn;
+      }
+    if (diff <= 1e-15) break;
+  }
+  return true;
+}
+
+// Mooney-Rivlin constants from (mu, lambda) and the C01 share s:
+// C10 = (1 - s) mu / 2, C01 = s mu / 2, kappa = lambda + 2 mu / 3 (so the
+// small-strain limit is linear elasticity with the same mu and lambda).
+__device__ inline void mr_constants(double mu, double lam, double share, double &c10,
+                                    double &c01, double &kappa) {
+  c10 = (1.0 - share) * 0.5 * mu;
+  c01 = share * 0.5 * mu;
+  kappa = lam + 2.0 * mu / 3.0;
+}
+
+// HEX8, Mooney-Rivlin (MAT 3) or co-rotational (MAT 2).  One wavefront per
+// hexahedron, lane = (a, b) as in k_elem_hex.
+//   MAT 3: lanes 0..7 set up the Gauss points; then the 72 (point, direction)
+//     columns of dP/dF are spread over the 64 lanes (dual numbers, FP64);
+//     lane (a, b) accumulates K_ab = sum_q g_a,j A_ijkl g_b,l; lane (a, b)
+//     takes the force share of Gauss point b.
+//   MAT 2: lanes 0..7 set up the Gauss points (gradients, weights), lane 0
+//     the rotation R of F at the element centre; lanes 0..7 rotate their
+//     node back, d_n = R^T (x_n - x_0) - (X_n - X_0); lane (a, b) forms the
+//     linear-elastic block K0_ab, K_ab = R K0_ab R^T and the force share
+//     R K0_ab d_b.
+template <typename T, int MAT, bool COMPACT>
+__global__ __launch_bounds__(256) void k_elem_hex_x(
+    int64_t n_elems, const int32_t *__restrict__ conn, const uint8_t *__restrict__ slot,
+    const int32_t *__restrict__ smap, const int32_t *__restrict__ row_ptr,
+    const double *__restrict__ X, const double *__restrict__ q, const double *__restrict__ v,
+    const double *__restrict__ Ev, const uint8_t *__restrict__ dof_fixed, ElemParams prm,
+    T *__restrict__ A, double *__restrict__ bvec, T *__restrict__ ebuf,
+    double *__restrict__ rbuf, PcgState *state) {
+  constexpr int NW = 4;
+  constexpr int NA = MAT == 3 ? 81 : 1;
+  __shared__ T s_x[NW][8][3], s_u[NW][8][3], s_v[NW][8][3];
+  __shared__ T s_g[NW][8][8][3], s_dv[NW][8];
+  __shared__ double s_H[NW][8][9];
+  __shared__ T s_A[NW][8][NA], s_P[NW][8][9];
+  __shared__ double s_R[NW][9];
+  __shared__ T s_Rt[NW][9], s_d[NW][8][3];
+  __shared__ int s_node[NW][8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * NW + w;
+  const bool valid = e < n_elems;
+  const int a = lane >> 3, b = lane & 7;
+
+  if (valid && lane < 8) {
+    const int nd = conn[e * 8 + lane];
+    const int n0 = conn[e * 8];
+    s_node[w][lane] = nd;
+    for (int i = 0; i < 3; ++i) {
+      s_x[w][lane][i] = (T)(X[3 * nd + i] - X[3 * n0 + i]);
+      s_u[w][lane][i] = (T)(q[3 * nd + i] - X[3 * nd + i]);
+      s_v[w][lane][i] = (T)v[3 * nd + i];
+    }
+  }
+  __syncthreads();
+  const double Ee = valid ? Ev[e] : 0.0;
+  const double nu = prm.nu;
+  const double mu = Ee / (2.0 * (1.0 + nu));
+  const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const T g1 = T(0.57735026918962576451);  // 1/sqrt(3)
+  if (valid && lane < 8) {
+    const int gp = lane;
+    const T xi[3] = {(gp & 1) ? g1 : -g1, (gp & 2) ? g1 : -g1, (gp & 4) ? g1 : -g1};
+    T dN[8][3];
+    for (int n = 0; n < 8; ++n) {
+      const T s0 = (T)c_hex_sign[n][0], s1 = (T)c_hex_sign[n][1], s2 = (T)c_hex_sign[n][2];
+      const T t0 = T(1) + s0 * xi[0], t1 = T(1) + s1 * xi[1], t2 = T(1) + s2 * xi[2];
+      dN[n][0] = T(0.125) * s0 * t1 * t2;
+      dN[n][1] = T(0.125) * s1 * t0 * t2;
+      dN[n][2] = T(0.125) * s2 * t0 * t1;
+    }
+    T J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int n = 0; n < 8; ++n)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[i * 3 + j] += s_x[w][n][i] * dN[n][j];
+    const T dJ = det3(J);
+    if (!(dJ > T(0))) atomicOr(&state->elem_status, 1);
+    T Ji[9];
+    inv3(J, dJ, Ji);
+    double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int n = 0; n < 8; ++n) {
+      T g[3];
+      for (int i = 0; i < 3; ++i)
+        g[i] = dN[n][0] * Ji[0 * 3 + i] + dN[n][1] * Ji[1 * 3 + i] + dN[n][2] * Ji[2 * 3 + i];
+      for (int i = 0; i < 3; ++i) s_g[w][gp][n][i] = g[i];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[i * 3 + j] += (double)s_u[w][n][i] * (double)g[j];
+    }
+    for (int m = 0; m < 9; ++m) s_H[w][gp][m] = H[m];
+    s_dv[w][gp] = dJ;
+    if (MAT == 2 && gp == 0) {
+      // deformation gradient at the centre: dN_n(0) = sign_n / 8
+      T Jc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+      for (int n = 0; n < 8; ++n)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) Jc[i * 3 + j] += s_x[w][n][i] * T(0.125) * (T)c_hex_sign[n][j];
+      T Jci[9];
+      inv3(Jc, det3(Jc), Jci);
+      double Fc[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+      for (int n = 0; n < 8; ++n)
+        for (int j = 0; j < 3; ++j) {
+          const double gc = 0.125 * (c_hex_sign[n][0] * (double)Jci[j] +
+                                     c_hex_sign[n][1] * (double)Jci[3 + j] +
+                                     c_hex_sign[n][2] * (double)Jci[6 + j]);
+          for (int i = 0; i < 3; ++i) Fc[i * 3 + j] += (double)s_u[w][n][i] * gc;
+        }
+      double R[9];
+      if (!polar_rotation(Fc, R)) atomicOr(&state->elem_status, 1);
+      for (int m = 0; m < 9; ++m) s_R[w][m] = R[m];
+    }
+  }
+  __syncthreads();
+  if (MAT == 3) {
+    double c10, c01, kappa;
+    mr_constants(mu, lam, prm.mr_c01_share, c10, c01, kappa);
+    for (int task = lane; task < 72; task += 64) {
+      const int gp = task / 9, dir = task - 9 * (task / 9);
+      if (!valid) break;
+      double Acol[9], P[9];
+      const double Jg = mr_column(s_H[w][gp], dir, c10, c01, kappa, (double)s_dv[w][gp], Acol, P);
+      if (!(Jg > 0.0)) {
+        if (dir == 0) atomicOr(&state->elem_status, 1);
+        for (int m = 0; m < 9; ++m) Acol[m] = P[m] = 0.0;
+      }
+      for (int m = 0; m < 9; ++m) s_A[w][gp][m * 9 + dir] = (T)Acol[m];
+      if (dir == 0)
+        for (int m = 0; m < 9; ++m) s_P[w][gp][m] = (T)P[m];
+    }
+  } else {
+    if (valid && lane < 8) {
+      // node lane: d_n = R^T (x_n - x_0) - (X_n - X_0)
+      //               = (R^T - I)(X_n - X_0) + R^T (u_n - u_0)
+      const double *R = s_R[w];
+      double dx[3], du[3];
+      for (int i = 0; i < 3; ++i) {
+        dx[i] = (double)s_x[w][lane][i];
+        du[i] = (double)s_u[w][lane][i] - (double)s_u[w][0][i];
+      }
+      for (int i = 0; i < 3; ++i) {
+        double r = 0.0;
+        for (int j = 0; j < 3; ++j)
+          r += (R[j * 3 + i] - (i == j ? 1.0 : 0.0)) * dx[j] + R[j * 3 + i] * du[j];
+        s_d[w][lane][i] = (T)r;
+      }
+      if (lane == 0)
+        for (int m = 0; m < 9; ++m) s_Rt[w][m] = (T)R[m];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+
+  T K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T Mab = 0, fa[3] = {0, 0, 0};
+  const T rho = (T)prm.rho;
+  const T tmu = (T)mu, tlam = (T)lam;
+  for (int gp = 0; gp < 8; ++gp) {
+    const T *ga = s_g[w][gp][a], *gb = s_g[w][gp][b];
+    if (MAT == 3) {
+      const T *Ag = s_A[w][gp];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) {
+          T acc = 0;
+          for (int j = 0; j < 3; ++j) {
+            const T *Ar = Ag + (i * 3 + j) * 9 + k * 3;
+            acc += ga[j] * (Ar[0] * gb[0] + Ar[1] * gb[1] + Ar[2] * gb[2]);
+          }
+          K[i * 3 + k] += acc;
+        }
+    } else {
+      // linear-elastic block: dV [lam g_a g_b^T + mu g_b g_a^T + mu (g_a.g_b) I]
+      const T dv = s_dv[w][gp];
+      const T gg = ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          K[i * 3 + j] += dv * (tlam * ga[i] * gb[j] + tmu * gb[i] * ga[j]);
+      K[0] += dv * tmu * gg;
+      K[4] += dv * tmu * gg;
+      K[8] += dv * tmu * gg;
+    }
+    const T xi0 = (gp & 1) ? g1 : -g1, xi1 = (gp & 2) ? g1 : -g1, xi2 = (gp & 4) ? g1 : -g1;
+    const T Na = T(0.125) * (T(1) + (T)c_hex_sign[a][0] * xi0) *
+                 (T(1) + (T)c_hex_sign[a][1] * xi1) * (T(1) + (T)c_hex_sign[a][2] * xi2);
+    const T Nb = T(0.125) * (T(1) + (T)c_hex_sign[b][0] * xi0) *
+                 (T(1) + (T)c_hex_sign[b][1] * xi1) * (T(1) + (T)c_hex_sign[b][2] * xi2);
+    Mab += rho * Na * Nb * s_dv[w][gp];
+  }
+  if (MAT == 3) {
+    // force share: Gauss point b of node a
+    const T *P = s_P[w][b];
+    const T *g = s_g[w][b][a];
+    for (int i = 0; i < 3; ++i) fa[i] = P[i * 3] * g[0] + P[i * 3 + 1] * g[1] + P[i * 3 + 2] * g[2];
+  } else {
+    // K0_ab d_b, rotated; then K_ab = R K0_ab R^T
+    const T *R = s_Rt[w];
+    const T *d = s_d[w][b];
+    T kd[3];
+    for (int i = 0; i < 3; ++i) kd[i] = K[i * 3] * d[0] + K[i * 3 + 1] * d[1] + K[i * 3 + 2] * d[2];
+    for (int i = 0; i < 3; ++i) fa[i] = R[i * 3] * kd[0] + R[i * 3 + 1] * kd[1] + R[i * 3 + 2] * kd[2];
+    T RK[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        RK[i * 3 + j] = R[i * 3] * K[j] + R[i * 3 + 1] * K[3 + j] + R[i * 3 + 2] * K[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        K[i * 3 + j] = RK[i * 3] * R[j * 3] + RK[i * 3 + 1] * R[j * 3 + 1] + RK[i * 3 + 2] * R[j * 3 + 2];
+  }
+  const T h = (T)prm.h, al = (T)prm.alpha, be = (T)prm.beta;
+  const T cM = T(1) + h * al, cK = h * (be + h), cKv = be + h;
+  const T *vb = s_v[w][b];
+  const T grav[3] = {(T)prm.gx, (T)prm.gy, (T)prm.gz};
+  T Ablk[9], rhs[3];
+  for (int i = 0; i < 3; ++i) {
+    T kv = 0;
+    for (int j = 0; j < 3; ++j) {
+      Ablk[i * 3 + j] = cK * K[i * 3 + j];
+      kv += K[i * 3 + j] * vb[j];
+    }
+    Ablk[i * 4] += cM * Mab;
+    rhs[i] = Mab * grav[i] - fa[i] - al * Mab * vb[i] - cKv * kv;
+  }
+  scatter<T, COMPACT, 8>(e, a, b, s_node[w][a], Ablk, rhs, slot, smap, row_ptr, dof_fixed, A,
+                         bvec, ebuf, rbuf);
+}
+
+// TET4, Mooney-Rivlin (MAT 3) or co-rotational (MAT 2): 16 lanes per
+// tetrahedron, lane = (a, b), one quadrature point.  MAT 3: lanes 0..8 of the
+// tetrahedron compute the nine columns of dP/dF; MAT 2: lane 0 computes R,
+// lanes 0..3 rotate their node back.
+template <typename T, int MAT, bool COMPACT>
+__global__ __launch_bounds__(256) void k_elem_tet_x(
+    int64_t n_elems, const int32_t *__restrict__ conn, const uint8_t *__restrict__ slot,
+    const int32_t *__restrict__ smap, const int32_t *__restrict__ row_ptr,
+    const double *__restrict__ X, const double *__restrict__ q, const double *__restrict__ v,
+    const double *__restrict__ Ev, const uint8_t *__restrict__ dof_fixed, ElemParams prm,
+    T *__restrict__ A, double *__restrict__ bvec, T *__restrict__ ebuf,
+    double *__restrict__ rbuf, PcgState *state) {
+  constexpr int NT = 16;  // tets per block
+  constexpr int NA = MAT == 3 ? 81 : 1;
+  __shared__ T s_x[NT][4][3], s_u[NT][4][3], s_v[NT][4][3];
+  __shared__ T s_A[NT][NA], s_P[NT][9], s_Rt[NT][9], s_d[NT][4][3];
+  __shared__ double s_R[NT][9];
+  __shared__ int s_node[NT][4];
+  const int t = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+  const int64_t e = (int64_t)blockIdx.x * NT + t;
+  const bool valid = e < n_elems;
+  const int a = l16 >> 2, b = l16 & 3;
+  if (valid && l16 < 4) {
+    const int nd = conn[e * 4 + l16];
+    const int n0 = conn[e * 4];
+    s_node[t][l16] = nd;
+    for (int i = 0; i < 3; ++i) {
+      s_x[t][l16][i] = (T)(X[3 * nd + i] - X[3 * n0 + i]);
+      s_u[t][l16][i] = (T)(q[3 * nd + i] - X[3 * nd + i]);
+      s_v[t][l16][i] = (T)v[3 * nd + i];
+    }
+  }
+  __syncthreads();
+  const double Ee = valid ? Ev[e] : 0.0;
+  const double nu = prm.nu;
+  const double mu = Ee / (2.0 * (1.0 + nu));
+  const double lam = Ee * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  T g[4][3], V = T(0);
+  double H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (valid) {
+    T Dm[9];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) Dm[i * 3 + k] = s_x[t][k + 1][i];
+    const T det = det3(Dm);
+    if (!(det > T(0)) && l16 == 0) atomicOr(&state->elem_status, 1);
+    T Di[9];
+    inv3(Dm, det, Di);
+    V = det / T(6);
+    for (int i = 0; i < 3; ++i) {
+      g[1][i] = Di[0 * 3 + i];
+      g[2][i] = Di[1 * 3 + i];
+      g[3][i] = Di[2 * 3 + i];
+      g[0][i] = -(g[1][i] + g[2][i] + g[3][i]);
+    }
+    for (int n = 0; n < 4; ++n)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) H[i * 3 + j] += (double)s_u[t][n][i] * (double)g[n][j];
+    if (MAT == 3 && l16 < 9) {
+      double c10, c01, kappa, Acol[9], P[9];
+      mr_constants(mu, lam, prm.mr_c01_share, c10, c01, kappa);
+      const double Jg = mr_column(H, l16, c10, c01, kappa, (double)V, Acol, P);
+      if (!(Jg > 0.0)) {
+        if (l16 == 0) atomicOr(&state->elem_status, 1);
+        for (int m = 0; m < 9; ++m) Acol[m] = P[m] = 0.0;
+      }
+      for (int m = 0; m < 9; ++m) s_A[t][m * 9 + l16] = (T)Acol[m];
+      if (l16 == 0)
+        for (int m = 0; m < 9; ++m) s_P[t][m] = (T)P[m];
+    }
+    if (MAT == 2 && l16 == 0) {
+      double F[9], R[9];
+      for (int m = 0; m < 9; ++m) F[m] = H[m] + ((m == 0 || m == 4 || m == 8) ? 1.0 : 0.0);
+      if (!polar_rotation(F, R)) atomicOr(&state->elem_status, 1);
+      for (int m = 0; m < 9; ++m) s_R[t][m] = R[m];
+    }
+  }
+  __syncthreads();
+  if (MAT == 2 && valid && l16 < 4) {
+    const double *R = s_R[t];
+    double dx[3], du[3];
+    for (int i = 0; i < 3; ++i) {
+      dx[i] = (double)s_x[t][l16][i];
+      du[i] = (double)s_u[t][l16][i] - (double)s_u[t][0][i];
+    }
+    for (int i = 0; i < 3; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < 3; ++j)
+        r += (R[j * 3 + i] - (i == j ? 1.0 : 0.0)) * dx[j] + R[j * 3 + i] * du[j];
+      s_d[t][l16][i] = (T)r;
+    }
+    if (l16 == 0)
+      for (int m = 0; m < 9; ++m) s_Rt[t][m] = (T)R[m];
+  }
+  __syncthreads();
+  if (!valid) return;
+  T K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, fa[3];
+  if (MAT == 3) {
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        T acc = 0;
+        for (int j = 0; j < 3; ++j) {
+          const T *Ar = s_A[t] + (i * 3 + j) * 9 + k * 3;
+          acc += g[a][j] * (Ar[0] * g[b][0] + Ar[1] * g[b][1] + Ar[2] * g[b][2]);
+        }
+        K[i * 3 + k] = acc;
+      }
+    const T *P = s_P[t];
+    for (int i = 0; i < 3; ++i)
+      fa[i] = T(0.25) * (P[i * 3] * g[a][0] + P[i * 3 + 1] * g[a][1] + P[i * 3 + 2] * g[a][2]);
+  } else {
+    const T tmu = (T)mu, tlam = (T)lam;
+    const T gg = g[a][0] * g[b][0] + g[a][1] * g[b][1] + g[a][2] * g[b][2];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) K[i * 3 + j] = V * (tlam * g[a][i] * g[b][j] + tmu * g[b][i] * g[a][j]);
+    K[0] += V * tmu * gg;
+    K[4] += V * tmu * gg;
+    K[8] += V * tmu * gg;
+    const T *R = s_Rt[t];
+    const T *d = s_d[t][b];
+    T kd[3];
+    for (int i = 0; i < 3; ++i) kd[i] = K[i * 3] * d[0] + K[i * 3 + 1] * d[1] + K[i * 3 + 2] * d[2];
+    for (int i = 0; i < 3; ++i) fa[i] = R[i * 3] * kd[0] + R[i * 3 + 1] * kd[1] + R[i * 3 + 2] * kd[2];
+    T RK[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        RK[i * 3 + j] = R[i * 3] * K[j] + R[i * 3 + 1] * K[3 + j] + R[i * 3 + 2] * K[6 + j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        K[i * 3 + j] = RK[i * 3] * R[j * 3] + RK[i * 3 + 1] * R[j * 3 + 1] + RK[i * 3 + 2] * R[j * 3 + 2];
+  }
+  const T Mab = (T)prm.rho * V * (a == b ? T(2) : T(1)) / T(20);
+  const T h = (T)prm.h, al = (T)prm.alpha, be = (T)prm.beta;
+  const T cM = T(1) + h * al, cK = h * (be + h), cKv = be + h;
+  const T *vb = s_v[t][b];
+  const T grav[3] = {(T)prm.gx, (T)prm.gy, (T)prm.gz};
+  T Ablk[9], rhs[3];
+  for (int i = 0; i < 3; ++i) {
+    T kv = 0;
+    for (int j = 0; j < 3; ++j) {
+      Ablk[i * 3 + j] = cK * K[i * 3 + j];
+      kv += K[i * 3 + j] * vb[j];
+    }
+    Ablk[i * 4] += cM * Mab;
+    rhs[i] = Mab * grav[i] - fa[i] - al * Mab * vb[i] - cKv * kv;
+  }
+  scatter<T, COMPACT, 4>(e, a, b, s_node[t][a], Ablk, rhs, slot, smap, row_ptr, dof_fixed, A,
+                         bvec, ebuf, rbuf);
+}
+
 // ------------------------------------------------------------------ TET4
 template <typename T, int MAT, bool COMPACT>
 __global__ __launch_bounds__(256) void k_elem_tet(
@@ -485,23 +962,41 @@ void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_
 #define FE_HEX(MAT, CMP)                                                                    \
   k_elem_hex<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
                                                    v, E, dof_fixed, prm, A, b, ebuf, rbuf, state)
+#define FE_HEXX(MAT, CMP)                                                                   \
+  k_elem_hex_x<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
+                                                     v, E, dof_fixed, prm, A, b, ebuf, rbuf,   \
+                                                     state)
     if (prm.material == 0) {
       if (compact) FE_HEX(0, true); else FE_HEX(0, false);
-    } else {
+    } else if (prm.material == 1) {
       if (compact) FE_HEX(1, true); else FE_HEX(1, false);
+    } else if (prm.material == 2) {
+      if (compact) FE_HEXX(2, true); else FE_HEXX(2, false);
+    } else {
+      if (compact) FE_HEXX(3, true); else FE_HEXX(3, false);
     }
 #undef FE_HEX
+#undef FE_HEXX
   } else {
     const unsigned blocks = (unsigned)((n_elems + 15) / 16);
 #define FE_TET(MAT, CMP)                                                                    \
   k_elem_tet<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
                                                    v, E, dof_fixed, prm, A, b, ebuf, rbuf, state)
+#define FE_TETX(MAT, CMP)                                                                   \
+  k_elem_tet_x<T, MAT, CMP><<<blocks, 256, 0, st>>>(n_elems, conn, slot, smap, row_ptr, X, q, \
+                                                     v, E, dof_fixed, prm, A, b, ebuf, rbuf,   \
+                                                     state)
     if (prm.material == 0) {
       if (compact) FE_TET(0, true); else FE_TET(0, false);
-    } else {
+    } else if (prm.material == 1) {
       if (compact) FE_TET(1, true); else FE_TET(1, false);
+    } else if (prm.material == 2) {
+      if (compact) FE_TETX(2, true); else FE_TETX(2, false);
+    } else {
+      if (compact) FE_TETX(3, true); else FE_TETX(3, false);
     }
 #undef FE_TET
+#undef FE_TETX
   }
 }
 

@@ -45,9 +45,10 @@ class Params:
     """Physical parameters; E and f_nodal are kept as device tensors."""
 
     def __init__(self, h, alpha, beta, rho, nu, material, gravity, E, f_nodal=None,
-                 device="cuda"):
+                 device="cuda", mr_c01_share=0.25):
         self.h, self.alpha, self.beta, self.rho, self.nu = h, alpha, beta, rho, nu
         self.material = int(material)
+        self.mr_c01_share = float(mr_c01_share)
         self.gravity = [float(g) for g in gravity]
         self.E = torch.as_tensor(np.asarray(E), dtype=torch.float64, device=device).contiguous() \
             if not isinstance(E, torch.Tensor) else E.to(device=device, dtype=torch.float64).contiguous()
@@ -65,6 +66,7 @@ class Params:
             p.gravity[i] = self.gravity[i]
         p.E = self.E.data_ptr()
         p.f_nodal = self.f_nodal.data_ptr() if self.f_nodal is not None else None
+        p.mr_c01_share = self.mr_c01_share
         return p
 
     def with_E(self, E):
@@ -446,7 +448,7 @@ class Simulation:
         self.ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec, leaf_nodes, n_threads, device,
                              factor_on_gpu=factor_on_gpu, factor_max_blocks=factor_max_blocks)
         self.params = Params(w.h, w.alpha, w.beta, w.rho, w.nu, w.material, w.gravity, w.E,
-                             w.f_nodal, device)
+                             w.f_nodal, device, getattr(w, "mr_c01_share", 0.25))
         self.device = device
         self.q = torch.as_tensor(w.X.reshape(-1).copy(), device=device)
         self.v = torch.zeros_like(self.q)

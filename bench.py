@@ -185,6 +185,31 @@ def _other_workloads():
     return out
 
 
+def _materials(steps=30, warmup=10):
+    """The paper's other element models on the benchmark workload (Sec. 3.1:
+    co-rotational and Mooney-Rivlin): mixed steps/s on the same schedule and
+    the duration of one assembly (element kernel + gather)."""
+    import dataclasses
+
+    import synth
+    from paper_2306_05893_amd import FE_COROTATIONAL, FE_MOONEY_RIVLIN, FE_PREC_MIXED
+
+    out = {}
+    for name, mat in (("corotational", FE_COROTATIONAL), ("mooney_rivlin", FE_MOONEY_RIVLIN)):
+        w = dataclasses.replace(synth.make("hex_beam"), material=mat)
+        r = _timed_run(w, FE_PREC_MIXED, steps, warmup)
+        kt = _kernel_profile(r["sim"], n_apply=0, n_spmv=0, n_assemble=10)
+        r["sim"].ctx.close()
+        el = kt["element"]
+        out[name] = {"steps_per_s": round(r["steps_per_s"], 2),
+                     "cg_it_mean": round(r["cg_it_mean"], 2),
+                     "factor_lag_mean": round(r["factor_lag_mean"], 1),
+                     "assembly_us": round(1e3 * el["ms"] / max(el["count"], 1), 1)}
+        print(f"[bench] {name}: {out[name]['steps_per_s']} steps/s, assembly "
+              f"{out[name]['assembly_us']} us", file=sys.stderr, flush=True)
+    return out
+
+
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 
 
@@ -368,6 +393,8 @@ def main():
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--factor-only", type=int, default=0, metavar="N",
                     help="only time N standalone GPU refactorisations of the hex beam")
+    ap.add_argument("--materials-only", action="store_true",
+                    help="only run the co-rotational and Mooney-Rivlin legs")
     ap.add_argument("--contact-only", action="store_true",
                     help="only run the contact measurements (compliance matrix, PGS)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -382,6 +409,9 @@ def main():
         return
     if args.contact_only:
         print(json.dumps({"contact": _contact()}))
+        return
+    if args.materials_only:
+        print(json.dumps({"materials": _materials()}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -438,6 +468,7 @@ def main():
         print(f"[bench] adjoint {adj_rate:.1f} steps/s", file=sys.stderr, flush=True)
         others = _other_workloads()
         contact = _contact()
+        materials = _materials()
         extras = {"warm_start_steps_per_s": round(warm["steps_per_s"], 3),
                   "warm_start_cg_it_mean": round(warm["cg_it_mean"], 2),
                   "host_factor_steps_per_s": round(host["steps_per_s"], 3),
@@ -447,7 +478,7 @@ def main():
                   "fp64_ms_per_step": round(fp64["ms_per_step"], 4),
                   "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
                   "adjoint_steps_per_s": round(adj_rate, 3), "adjoint_finite": adj_ok,
-                  "other_workloads": others, "contact": contact}
+                  "other_workloads": others, "contact": contact, "materials": materials}
 
     # per-kernel figures from HIP events recorded around every launch
     kern = {}

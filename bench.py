@@ -210,6 +210,41 @@ def _materials(steps=30, warmup=10):
     return out
 
 
+def _topology():
+    """Full assembly on a topology change (Sec. 4.2) on the hex beam: the
+    keepStruct test on the GPU when nothing changed, and the rebuild of
+    pattern, map, ordering, factor structure and device workspace after a cut
+    (one layer of 400 elements removed; host work plus the upload), followed
+    by the first assembly on the new context."""
+    import torch
+
+    import synth
+    from paper_2306_05893_amd import FE_PREC_MIXED
+    from paper_2306_05893_amd.sim import Simulation
+
+    w = synth.make("hex_beam")
+    sim = Simulation(w, prec=FE_PREC_MIXED, device="cuda", factor_on_gpu=True)
+    sim.ctx.assemble(sim.params, sim.q, sim.v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        assert sim.set_topology(w.conn, w.E) is False
+    t_keep = (time.perf_counter() - t0) / 10
+    zc = w.X[w.conn][:, :, 2].mean(axis=1) / w.spacing
+    keep = ~((zc >= 40) & (zc < 41))
+    t0 = time.perf_counter()
+    assert sim.set_topology(w.conn[keep], w.E[keep]) is True
+    sim.ctx.assemble(sim.params, sim.q, sim.v)
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    out = {"keepstruct_check_ms": round(1e3 * t_keep, 3), "full_assembly_ms": round(1e3 * t_full, 1),
+           "elements_removed": int((~keep).sum()), "nnz_after": int(sim.ctx.sizes.nnz)}
+    sim.ctx.close()
+    print(f"[bench] topology: keepStruct check {out['keepstruct_check_ms']} ms, full assembly "
+          f"{out['full_assembly_ms']} ms", file=sys.stderr, flush=True)
+    return out
+
+
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 
 
@@ -393,6 +428,8 @@ def main():
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--factor-only", type=int, default=0, metavar="N",
                     help="only time N standalone GPU refactorisations of the hex beam")
+    ap.add_argument("--topology-only", action="store_true",
+                    help="only time the keepStruct test and a full assembly after a cut")
     ap.add_argument("--materials-only", action="store_true",
                     help="only run the co-rotational and Mooney-Rivlin legs")
     ap.add_argument("--contact-only", action="store_true",
@@ -412,6 +449,9 @@ def main():
         return
     if args.materials_only:
         print(json.dumps({"materials": _materials()}))
+        return
+    if args.topology_only:
+        print(json.dumps({"topology": _topology()}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -469,6 +509,7 @@ def main():
         others = _other_workloads()
         contact = _contact()
         materials = _materials()
+        topology = _topology()
         extras = {"warm_start_steps_per_s": round(warm["steps_per_s"], 3),
                   "warm_start_cg_it_mean": round(warm["cg_it_mean"], 2),
                   "host_factor_steps_per_s": round(host["steps_per_s"], 3),
@@ -478,7 +519,8 @@ def main():
                   "fp64_ms_per_step": round(fp64["ms_per_step"], 4),
                   "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
                   "adjoint_steps_per_s": round(adj_rate, 3), "adjoint_finite": adj_ok,
-                  "other_workloads": others, "contact": contact, "materials": materials}
+                  "other_workloads": others, "contact": contact, "materials": materials,
+                  "topology": topology}
 
     # per-kernel figures from HIP events recorded around every launch
     kern = {}

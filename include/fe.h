@@ -330,6 +330,23 @@ int fe_constraint_apply(fe_ctx *ctx, int32_t k, const int32_t *h_row_ptr, const 
 int fe_pgs(fe_ctx *ctx, int32_t k, const double *W, const double *c, double *lam,
            int32_t max_sweeps, double tol, double *info, void *stream);
 
+/* keepStruct test of the fast assembly (Sec. 4, Alg. "add"): does a
+ * candidate fill sequence differ from the one the context's pattern and map
+ * were built from?  The fill order is a function of the element connectivity
+ * (element-major, local node order) and of the fixed DOFs, so they are
+ * compared entry by entry on the GPU.
+ *   n_elems    elements of the candidate (same element type)
+ *   conn       device [n_elems * nen] candidate connectivity
+ *   fixed_dof  device [n_dofs] candidate Dirichlet flags, NULL = unchanged
+ *   changed    host out: 0 = same fill order, the map stays valid (fast
+ *              assembly); 1 = it changed (e.g. elements removed by cutting,
+ *              or a node order permuted), and the pattern, the map and the
+ *              factor structure must be rebuilt: the full assembly is a new
+ *              context from fe_build_pattern with the new mesh
+ * Synchronises `stream`. */
+int fe_structure_changed(fe_ctx *ctx, int64_t n_elems, const int32_t *conn,
+                         const uint8_t *fixed_dof, int32_t *changed, void *stream);
+
 /* Host-only check of the factorisation (no GPU): factor the FP64 CSR values
  * A_host (host [nnz]) with the context's ordering and supernodes, then apply
  * z = P^{-1} r on the host with the same explicit-inverse panels and the same

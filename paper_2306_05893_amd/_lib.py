@@ -108,6 +108,7 @@ SIGNATURES = {
     "fe_constraint_apply": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, C.c_int32,
                                       C.c_double, _P, C.c_double, _P, _P, _P]),
     "fe_pgs": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, C.c_double, _P, _P]),
+    "fe_structure_changed": (C.c_int, [_P, C.c_int64, _P, _P, C.POINTER(C.c_int32), _P]),
     "fe_set_graphs": (C.c_int, [_P, C.c_int32]),
     "fe_set_kernel_timing": (C.c_int, [_P, C.c_int32]),
     "fe_kernel_times": (C.c_int, [_P, _P, _P, _P, C.c_int32]),

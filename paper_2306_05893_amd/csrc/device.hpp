@@ -51,6 +51,12 @@ void launch_assembly_init(hipStream_t st, int64_t nnz, T *A, int64_t n_fixed,
                           const int32_t *fixed_diag_slot, int64_t n, double *b,
                           const double *f_nodal, const uint8_t *dof_fixed, bool zero_A);
 
+// keepStruct: *flag = 1 if conn differs from ref_conn or (fixed != NULL)
+// fixed differs from ref_fixed.
+void launch_struct_cmp(hipStream_t st, int64_t n_conn, const int32_t *conn, const int32_t *ref_conn,
+                       int64_t n_dofs, const uint8_t *fixed, const uint8_t *ref_fixed,
+                       int *flag);
+
 // Element tangents + forces.  With the compact map (slot != NULL) the 3 x 3
 // blocks go to ebuf [E][nen*nen][9] and the RHS shares of the nodes to rbuf
 // [E][nen][3] (no atomics; launch_assembly_gather sums them into A and b);

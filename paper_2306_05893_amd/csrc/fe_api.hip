@@ -1462,6 +1462,27 @@ int fe_constraint_apply(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const in
   return herr_check(c, st);
 }
 
+int fe_structure_changed(fe_ctx *c, int64_t n_elems, const int32_t *conn,
+                         const uint8_t *fixed_dof, int32_t *changed, void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!changed || n_elems < 0 || (n_elems > 0 && !conn)) return c->fail(FE_EINVAL, "bad argument");
+  if (n_elems != c->P.n_elems) {  // another element count: another fill sequence
+    *changed = 1;
+    return FE_OK;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int *flag = c->d_herr + 1;  // second word of the error area
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  launch_struct_cmp(st, n_elems * c->nen, conn, c->d_conn, c->P.n, fixed_dof, c->d_dof_fixed,
+                    flag);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *changed = *c->h_flag ? 1 : 0;
+  return FE_OK;
+}
+
 int fe_pgs(fe_ctx *c, int32_t k, const double *W, const double *cvec, double *lam,
            int32_t max_sweeps, double tol, double *info, void *stream) {
   if (!c) return FE_EINVAL;

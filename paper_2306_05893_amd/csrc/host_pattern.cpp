@@ -120,6 +120,8 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
       }
     }
     if (P.col_idx.size() > (size_t)INT32_MAX) return "nnz exceeds int32 range";
+    if (P.col_idx.size() == (size_t)P.row_ptr[r])
+      return "a free DOF belongs to no element (its row of A would be empty)";
     P.row_ptr[r + 1] = (int32_t)P.col_idx.size();
   }
 

@@ -934,6 +934,15 @@ __global__ void k_set_fixed_diag(int64_t n_fixed, const int32_t *fds, T *A) {
   if (k < n_fixed) A[fds[k]] = T(1);
 }
 
+// keepStruct test of the fill order: flag[0] = 1 if any entry differs.
+template <typename U>
+__global__ void k_struct_cmp(int64_t n, const U *__restrict__ a, const U *__restrict__ b,
+                             int *flag) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    if (a[i] != b[i]) *flag = 1;
+}
+
 }  // namespace
 
 template <typename T>
@@ -998,6 +1007,15 @@ void launch_element(hipStream_t st, int elem_type, int64_t n_elems, const int32_
 #undef FE_TET
 #undef FE_TETX
   }
+}
+
+void launch_struct_cmp(hipStream_t st, int64_t n_conn, const int32_t *conn, const int32_t *ref_conn,
+                       int64_t n_dofs, const uint8_t *fixed, const uint8_t *ref_fixed,
+                       int *flag) {
+  auto grid = [](int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); };
+  if (n_conn > 0) k_struct_cmp<int32_t><<<grid(n_conn), 256, 0, st>>>(n_conn, conn, ref_conn, flag);
+  if (fixed && n_dofs > 0)
+    k_struct_cmp<uint8_t><<<grid(n_dofs), 256, 0, st>>>(n_dofs, fixed, ref_fixed, flag);
 }
 
 template <typename T>

@@ -415,6 +415,23 @@ class FEContext:
         x, st_corr = self.pcg_solve(A, rhs, x=x_free.clone(), rel_tol=rel_tol, max_it=max_it)
         return x, x_free, lam, W, {"free": st_free, "correction": st_corr, "pgs": info}
 
+    def structure_changed(self, conn, fixed=None):
+        """keepStruct test (Sec. 4): True if the element fill sequence
+        (device int32 connectivity, element-major) or the fixed DOFs (device
+        uint8, None = unchanged) differ from those of this context's map."""
+        self.bind()
+        if not (conn.is_cuda and conn.dtype == torch.int32 and conn.is_contiguous()):
+            raise ValueError("conn must be a contiguous int32 CUDA tensor")
+        if conn.numel() % self.nen:
+            raise ValueError("conn length is not a multiple of the element's node count")
+        if fixed is not None and not (fixed.is_cuda and fixed.dtype == torch.uint8
+                                      and fixed.numel() == self.sizes.n_dofs):
+            raise ValueError("fixed must be a uint8 CUDA tensor of n_dofs entries")
+        ch = C.c_int32()
+        self._chk(self.lib.fe_structure_changed(self.h, conn.numel() // self.nen, _ptr(conn),
+                                                _ptr(fixed), C.byref(ch), _stream()))
+        return bool(ch.value)
+
     def set_graphs(self, on=True):
         self._chk(self.lib.fe_set_graphs(self.h, 1 if on else 0))
 
@@ -450,8 +467,38 @@ class Simulation:
         self.params = Params(w.h, w.alpha, w.beta, w.rho, w.nu, w.material, w.gravity, w.E,
                              w.f_nodal, device, getattr(w, "mr_c01_share", 0.25))
         self.device = device
+        self._build = dict(prec=prec, leaf_nodes=leaf_nodes, n_threads=n_threads,
+                           factor_on_gpu=factor_on_gpu, factor_max_blocks=factor_max_blocks)
         self.q = torch.as_tensor(w.X.reshape(-1).copy(), device=device)
         self.v = torch.zeros_like(self.q)
+
+    def set_topology(self, conn, E, fixed=None):
+        """Change the element set (e.g. cutting removes elements) keeping
+        the nodes and the state (q, v).  The keepStruct test runs on the GPU;
+        if the fill sequence is unchanged nothing is rebuilt (fast assembly,
+        returns False).  Otherwise the pattern, map, ordering and factor
+        structure are rebuilt for the new mesh (full assembly, Sec. 4.2): a
+        new context is bound, the old one closed, and the factor schedule
+        starts again (returns True).  E: Young's modulus per new element."""
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        dconn = torch.as_tensor(conn.reshape(-1), device=self.device)
+        dfx = None if fx is None else torch.as_tensor(fx, device=self.device)
+        if not self.ctx.structure_changed(dconn, dfx):
+            return False
+        import dataclasses
+        w = dataclasses.replace(self.w, conn=conn, E=np.asarray(E, dtype=np.float64),
+                                fixed=self.w.fixed if fx is None else fx)
+        b = self._build
+        ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, b["prec"], b["leaf_nodes"],
+                        b["n_threads"], self.device, factor_on_gpu=b["factor_on_gpu"],
+                        factor_max_blocks=b["factor_max_blocks"])
+        ctx.bind()
+        self.ctx.close()
+        self.ctx = ctx
+        self.w = w
+        self.params = self.params.with_E(torch.as_tensor(w.E, device=self.device))
+        return True
 
     def opts(self, **kw):
         base = dict(rel_tol=self.w.rel_tol, max_it=2000, refresh=self.w.refresh, lag=self.w.lag)

@@ -121,6 +121,14 @@ def test_build_pattern_rejects_bad_input():
     assert ei.value.code == _lib.FE_EINVAL
     with pytest.raises(_lib.FEError):
         FEContext(w.X, w.conn, 6, w.fixed, device="cpu")
+    # a free node that belongs to no element (e.g. left behind by a cut)
+    X2 = np.vstack([w.X, [[1.0, 1.0, 1.0]]])
+    fx2 = np.concatenate([w.fixed, np.zeros(3, np.uint8)])
+    with pytest.raises(_lib.FEError) as ei:
+        FEContext(X2, w.conn, w.elem_type, fx2, device="cpu")
+    assert ei.value.code == _lib.FE_EINVAL and "no element" in str(ei.value)
+    fx2[-3:] = 1                                 # fixed: an identity row, accepted
+    FEContext(X2, w.conn, w.elem_type, fx2, device="cpu").close()
 
 
 def test_query_workspace_grows_with_precision():

@@ -102,6 +102,47 @@ def _kernel_profile(sim, n_apply=40, n_spmv=40, n_assemble=10):
     return kt
 
 
+def _roofline(kt):
+    """Per-kernel figures from the HIP events recorded around every launch,
+    and the roofline entry of the dominant sweep kernel."""
+    kern = {}
+    for name, d in kt.items():
+        if d["count"]:
+            kern[name] = {"launches": d["count"], "avg_us": 1e3 * d["ms"] / d["count"],
+                          "total_ms": d["ms"], "GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
+    dominant = max(("trisolve_fwd", "trisolve_bwd"), key=lambda n: kern[n]["total_ms"])
+    dk = kt[dominant]
+    achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _recorded_traffic(KERNEL_SYMBOL[dominant]),
+                "bytes_per_launch": dk["bytes"] / dk["count"],
+                "avg_launch_us": 1e3 * dk["ms"] / dk["count"]}
+    return kern, roofline
+
+
+def _kernel_pass_only():
+    """The event-timed kernel pass alone, on a context whose factor is that of
+    the assembled hex beam at rest: no CG iterations run, so a kernel trace of
+    this command holds the same sweep, SpMV and assembly launches as the
+    events (plus one untimed preconditioner application first)."""
+    import torch
+
+    import synth
+    from paper_2306_05893_amd import FE_PREC_MIXED
+    from paper_2306_05893_amd.sim import Simulation
+
+    w = synth.make("hex_beam")
+    sim = Simulation(w, prec=FE_PREC_MIXED, device="cuda", factor_on_gpu=True)
+    A, _ = sim.ctx.assemble(sim.params, sim.q, sim.v)
+    sim.ctx.factorize_now(A, 0)
+    torch.cuda.synchronize()
+    kt = _kernel_profile(sim)
+    sim.ctx.close()
+    kern, roofline = _roofline(kt)
+    print(json.dumps({"workload": "hex_beam", "kernels": kern, "roofline": roofline}))
+
+
 def _recorded_traffic(symbol):
     """HBM bytes per launch from the committed PMC record, or None when the
     kernel source has changed since the counters were taken."""
@@ -434,6 +475,8 @@ def main():
                     help="only run the co-rotational and Mooney-Rivlin legs")
     ap.add_argument("--contact-only", action="store_true",
                     help="only run the contact measurements (compliance matrix, PGS)")
+    ap.add_argument("--kernel-pass-only", action="store_true",
+                    help="only the event-timed kernel pass (factor of A at rest)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
@@ -443,6 +486,9 @@ def main():
         return
     if args.factor_only > 0:
         _factor_only(args.factor_only)
+        return
+    if args.kernel_pass_only:
+        _kernel_pass_only()
         return
     if args.contact_only:
         print(json.dumps({"contact": _contact()}))
@@ -522,20 +568,7 @@ def main():
                   "other_workloads": others, "contact": contact, "materials": materials,
                   "topology": topology}
 
-    # per-kernel figures from HIP events recorded around every launch
-    kern = {}
-    for name, d in kt.items():
-        if d["count"]:
-            kern[name] = {"launches": d["count"], "avg_us": 1e3 * d["ms"] / d["count"],
-                          "total_ms": d["ms"], "GBps": d["bytes"] / (d["ms"] * 1e-3) / 1e9}
-    dominant = max(("trisolve_fwd", "trisolve_bwd"), key=lambda n: kern[n]["total_ms"])
-    dk = kt[dominant]
-    achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _recorded_traffic(KERNEL_SYMBOL[dominant]),
-                "bytes_per_launch": dk["bytes"] / dk["count"],
-                "avg_launch_us": 1e3 * dk["ms"] / dk["count"]}
+    kern, roofline = _roofline(kt)
 
     cpu = None if args.no_cpu_baseline else _cpu_baseline()
     line = {

@@ -278,8 +278,10 @@ hipEvent_t take_event(fe_ctx *c) {
     c->ev_pool.pop_back();
     return e;
   }
+  // timing-only events: no system-scope fence on record, so the marker does
+  // not write back and invalidate the L2s between the timed kernels
   hipEvent_t e = nullptr;
-  (void)hipEventCreate(&e);
+  (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
   return e;
 }
 

@@ -167,6 +167,59 @@ __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_
 //    column, forward substitution with the unit lower factor of the block:
 //      x_r <- x_r - sum_{k<r} L_d[r][k] x_k.
 // blockIdx.y = front of the step; chunks of 256 rows / 256 columns.
+//
+// Both roles run the right-looking elimination order: for k, for c > k,
+// v[c] -= v[k] L_d[c][k].  The strictly lower entries of the block are
+// packed in LDS in exactly that order (pair (k, c) at kPairIdx(k, c)), so
+// the entries the next few dozen updates need are read as whole 8-entry
+// chunks, kRing - 1 chunks ahead of their use, into a register ring: the
+// LDS latency overlaps the arithmetic instead of stalling every update.
+constexpr int kPairs = NB * (NB - 1) / 2;
+constexpr int kChunk = 8;
+constexpr int kChunks = kPairs / kChunk;
+constexpr int kRing = 4;
+static_assert(kPairs % kChunk == 0, "the packed block splits into whole chunks");
+
+__host__ __device__ constexpr int kPairIdx(int k, int c) { return k * (2 * NB - k - 1) / 2 + (c - k - 1); }
+
+struct PairRing {
+  double2 r[kRing][kChunk / 2];
+  __device__ __forceinline__ void load(const double *P, int chunk) {
+    const double2 *src = reinterpret_cast<const double2 *>(P) + chunk * (kChunk / 2);
+#pragma unroll
+    for (int q = 0; q < kChunk / 2; ++q) r[chunk % kRing][q] = src[q];
+  }
+  __device__ __forceinline__ double at(int p) const {
+    const double2 w = r[(p / kChunk) % kRing][(p % kChunk) / 2];
+    return (p & 1) ? w.y : w.x;
+  }
+};
+
+// SCALE: the rows role (store f_k to W before l_k = f_k / d_k); otherwise
+// the X role (unit lower substitution only).  v[k] is final after step k and
+// goes out at once (out(k, v[k])), so the registers of the finished entries
+// are free for the ring.
+template <bool SCALE, typename Out>
+__device__ __forceinline__ void gf_subst(double (&v)[NB], const double *P, const double *dinv,
+                                         double *W, int64_t m, uint32_t i, Out out) {
+  PairRing ring;
+#pragma unroll
+  for (int j = 0; j < kRing - 1; ++j) ring.load(P, j);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (SCALE) (W + (int64_t)k * m)[i] = v[k];
+#pragma unroll
+    for (int c = k + 1; c < NB; ++c) {
+      const int p = kPairIdx(k, c);
+      if (p % kChunk == 0 && p / kChunk + kRing - 1 < kChunks) ring.load(P, p / kChunk + kRing - 1);
+      if (SCALE) v[c] -= v[k] * ring.at(p);
+      else v[c] -= ring.at(p) * v[k];
+    }
+    if (SCALE) v[k] *= dinv[k];
+    out(k, v[k]);
+  }
+}
+
 __device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base) {
   const int m = f.m, nc = f.nc;
   const int k1 = min(k0 + NB, nc), kb = k1 - k0;
@@ -174,19 +227,19 @@ __device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base
   const int first = rows_role ? k1 + bx * 256 : (bx - nrb) * 256;
   if (first >= (rows_role ? m : k1)) return;  // whole block past this front's work
   double *F = base + f.offF;
-  // the block, transposed (Lt[k][c] = L_d[c][k], column k of L_d contiguous)
-  // and padded to NB x NB with the identity, so that the unrolled loops
-  // below need no bounds tests
-  __shared__ double Lt[NB][NB + 2];
+  // strictly lower entries of the block in elimination order; the padding
+  // (k or c >= kb, last panel of a front) is the identity: zero entries and
+  // unit pivots, so that the unrolled loops below need no bounds tests
+  __shared__ __align__(16) double P[kPairs];
   __shared__ double dinv[NB];
   for (int idx = threadIdx.x; idx < NB * NB; idx += 256) {
-    const int c = idx % NB, k = idx / NB;
-    double x = c == k ? 1.0 : 0.0;
-    if (c >= k && c < kb) x = F[(int64_t)(k0 + k) * m + k0 + c];
-    Lt[k][c] = x;
+    const int k = idx / NB, c = idx % NB;
+    if (c > k) P[kPairIdx(k, c)] = c < kb ? F[(int64_t)(k0 + k) * m + k0 + c] : 0.0;
   }
-  __syncthreads();
-  if (threadIdx.x < NB) dinv[threadIdx.x] = 1.0 / Lt[threadIdx.x][threadIdx.x];
+  if (threadIdx.x < NB) {
+    const int k = threadIdx.x;
+    dinv[k] = k < kb ? 1.0 / F[(int64_t)(k0 + k) * m + k0 + k] : 1.0;
+  }
   __syncthreads();
   // Branch-free: loads clamped to the block's columns, and the stores of
   // the padding columns c >= kb (last panel of a front) sent to the unused
@@ -203,15 +256,8 @@ __device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base
       const double x = (Fk + (int64_t)min(c, kb - 1) * m)[i];
       v[c] = c < kb ? x : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      (W + (int64_t)k * m)[i] = v[k];
-#pragma unroll
-      for (int c = k + 1; c < NB; ++c) v[c] -= v[k] * Lt[k][c];
-      v[k] *= dinv[k];
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) ((c < kb ? Fk : W) + (int64_t)c * m)[i] = v[c];
+    gf_subst<true>(v, P, dinv, W, m, i,
+                   [&](int c, double x) { ((c < kb ? Fk : W) + (int64_t)c * m)[i] = x; });
   } else {
     if (i >= (uint32_t)k1) return;
     double *Xk = base + f.offX + (int64_t)k0 * nc;
@@ -220,15 +266,10 @@ __device__ void gf_rowops(const GfFront f, int k0, int bx, int nrb, double *base
       const double x = (Xk + (int64_t)min(r, kb - 1) * nc)[i];
       v[r] = r < kb ? x : 0.0;
     }
-#pragma unroll
-    for (int k = 0; k < NB; ++k)
-#pragma unroll
-      for (int r = k + 1; r < NB; ++r) v[r] -= Lt[k][r] * v[k];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) {
+    gf_subst<false>(v, P, dinv, W, m, i, [&](int r, double x) {
       double *dst = r < kb ? Xk + (int64_t)r * nc : W + (int64_t)r * m;
-      dst[i] = v[r];
-    }
+      dst[i] = x;
+    });
   }
 }
 

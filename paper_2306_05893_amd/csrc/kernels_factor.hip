@@ -326,22 +326,50 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
       acc[u][v] = x;
     }
   }
+  // staging: thread (r, kq) fills column r of rows k = kq + KS q of both
+  // operands; the loads are clamped into the front and unconditional, so a
+  // batch of them is in flight at once, and the out-of-range entries are
+  // zeroed when they are written to LDS
+  constexpr int KS = 256 / TL;            // k rows staged per pass of the block
+  constexpr int NPASS = 4;                // load batches per stage
+  constexpr int QH = KC / KS / NPASS;     // entries per thread per batch
+  const int sr = tid % TL, kq = tid / TL;
+  const bool iok = t.i0 + sr < imax, jok = t.j0 + sr < jmax;
+  const int si = min(t.i0 + sr, imax - 1), sj = min(t.j0 + sr, jmax - 1);
   for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
     const int kn = min(KC, kend - kc0);
     if (kc0 > kbeg) __syncthreads();
-    for (int idx = tid; idx < KC * TL; idx += 256) {
-      const int k = idx / TL, r = idx % TL;
-      const int kk = kc0 + k;
-      const int i = t.i0 + r;
-      sA[k][r] = (k < kn && i < imax) ? F[(int64_t)kk * m + i] : 0.0;
-      const int j = t.j0 + r;
-      double b = 0.0;
-      if (k < kn && j < jmax) {
-        if (reg == 0) b = W[(int64_t)(kk - k0) * m + j];
-        else if (reg == 2) b = F[(int64_t)kk * m + j] * F[(int64_t)kk * m + kk];
-        else b = X[(int64_t)kk * nc + j];
+#pragma unroll
+    for (int h = 0; h < NPASS; ++h) {
+      double a[QH], b[QH];
+      int kk[QH];
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        kk[q] = kc0 + min(kq + KS * (q + QH * h), kn - 1);
+        a[q] = F[(int64_t)kk[q] * m + si];
       }
-      sB[k][r] = b;
+      if (reg == 0) {
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] = W[(int64_t)(kk[q] - k0) * m + sj];
+      } else if (reg == 2) {
+        double dk[QH];
+#pragma unroll
+        for (int q = 0; q < QH; ++q) {
+          b[q] = F[(int64_t)kk[q] * m + sj];
+          dk[q] = F[(int64_t)kk[q] * m + kk[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] *= dk[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] = X[(int64_t)kk[q] * nc + sj];
+      }
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int k = kq + KS * (q + QH * h);
+        sA[k][sr] = (k < kn && iok) ? a[q] : 0.0;
+        sB[k][sr] = (k < kn && jok) ? b[q] : 0.0;
+      }
     }
     __syncthreads();
     for (int k = 0; k < kn; ++k) {

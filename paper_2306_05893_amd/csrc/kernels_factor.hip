@@ -41,7 +41,16 @@ __global__ void k_gf_init(const GfFront *fr, const int32_t *sn, int nf, double *
     const int64_t nF = (int64_t)f.m * f.nc, r = f.m - f.nc, nU = r * r;
     for (int64_t i = i0; i < nF; i += stride) base[f.offF + i] = 0.0;
     for (int64_t i = i0; i < nU; i += stride) base[f.offU + i] = 0.0;
-    for (int64_t i = i0; i < nF; i += stride) base[f.offX + i] = (i / f.nc == i % f.nc) ? 1.0 : 0.0;
+    // X = [I; 0] row-major: the unit entries are i = t (nc + 1), t < nc, all
+    // inside the leading nc x nc block (32-bit arithmetic when it fits)
+    const int64_t nc2 = (int64_t)f.nc * f.nc;
+    const uint32_t step = (uint32_t)f.nc + 1u;
+    const bool small = nc2 < ((int64_t)1 << 32);
+    for (int64_t i = i0; i < nF; i += stride) {
+      const bool unit =
+          i < nc2 && (small ? (uint32_t)i % step == 0u : i % (int64_t)step == 0);
+      base[f.offX + i] = unit ? 1.0 : 0.0;
+    }
   }
 }
 
@@ -54,10 +63,14 @@ __global__ void k_gf_scatter(int64_t n, const int32_t *a_csr, const int64_t *a_o
 }
 
 // extend-add: 32 x 32 tiles of the children's update matrices (tile per
-// block, stride gridDim.x)
-__global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, int64_t n_ext,
-                                                   const GfFront *fr, const int32_t *parent,
-                                                   const int32_t *rel, const int64_t *rel_off,
+// block, stride gridDim.x).  Thread (tx, ty) adds entries (i0 + tx,
+// j0 + ty + 8q), q < 4, of the lower triangle; the four loads of each kind
+// are clamped into the block and issued together before the atomics.
+__global__ __launch_bounds__(256) void k_gf_extend(const GfExt *__restrict__ ext, int64_t n_ext,
+                                                   const GfFront *__restrict__ fr,
+                                                   const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ rel,
+                                                   const int64_t *__restrict__ rel_off,
                                                    double *base) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int64_t e = blockIdx.x; e < n_ext; e += gridDim.x) {
@@ -70,15 +83,23 @@ __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *ext, int64_t n_e
     if (ii >= nr) continue;
     const int pi = rl[ii];
     const int rp = fp.m - fp.nc;
-    for (int jj = t.j0 + ty; jj < min(t.j0 + 32, nr); jj += 8) {
-      if (ii < jj) continue;
-      const double u = base[fc.offU + (int64_t)jj * nr + ii];
-      const int pj = rl[jj];
-      const int hi = max(pi, pj), lo = min(pi, pj);
+    double u[4];
+    int pj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = min(t.j0 + ty + 8 * q, nr - 1);
+      u[q] = base[fc.offU + (int64_t)jj * nr + ii];
+      pj[q] = rl[jj];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = t.j0 + ty + 8 * q;
+      if (jj >= min(t.j0 + 32, nr) || ii < jj) continue;
+      const int hi = max(pi, pj[q]), lo = min(pi, pj[q]);
       // own columns of the parent, or its update block
       const int64_t o = lo < fp.nc ? fp.offF + (int64_t)lo * fp.m + hi
                                    : fp.offU + (int64_t)(lo - fp.nc) * rp + (hi - fp.nc);
-      atomicAdd(base + o, u);
+      atomicAdd(base + o, u[q]);
     }
   }
 }
@@ -311,20 +332,31 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
   // touch consecutive rows; X outputs (row-major): thread columns tx + 16v
   const bool fout = reg == 0 || reg == 2;
   const int ra = fout ? tx : ty, cb = fout ? ty : tx;
+  // accumulators preloaded with the outputs' current values; the loads are
+  // clamped into the region and unconditional (entries outside it are
+  // computed on but never stored)
   double acc[R][R];
+  int ii[R], jj[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    const int i = t.i0 + ra + 16 * u;
+    ii[u] = min(t.i0 + ra + 16 * u, imax - 1);
+    jj[u] = min(t.j0 + cb + 16 * u, jmax - 1);
+  }
+  if (reg == 0) {
 #pragma unroll
-    for (int v = 0; v < R; ++v) {
-      const int j = t.j0 + cb + 16 * v;
-      double x = 0.0;
-      if (i < imax && j < jmax)
-        x = reg == 0 ? F[(int64_t)j * m + i]
-            : reg == 2 ? U[(j - nc) * ru + (i - nc)]
-                       : X[(int64_t)i * nc + j];
-      acc[u][v] = x;
-    }
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u][v] = F[(int64_t)jj[v] * m + ii[u]];
+  } else if (reg == 2) {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u][v] = U[(jj[v] - nc) * ru + (ii[u] - nc)];
+  } else {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) acc[u][v] = X[(int64_t)ii[u] * nc + jj[v]];
   }
   // staging: thread (r, kq) fills column r of rows k = kq + KS q of both
   // operands; the loads are clamped into the front and unconditional, so a
@@ -385,23 +417,31 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
         for (int v = 0; v < R; ++v) acc[u][v] = fma(-a[u], bb[v], acc[u][v]);
     }
   }
+  // stores: in range, and on or below the diagonal for the F outputs
+  if (reg == 0) {
 #pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int i = t.i0 + ra + 16 * u;
+    for (int u = 0; u < R; ++u)
 #pragma unroll
-    for (int v = 0; v < R; ++v) {
-      const int j = t.j0 + cb + 16 * v;
-      if (i < imax && j < jmax) {
-        if (fout) {
-          if (i >= j) {
-            if (reg == 0) F[(int64_t)j * m + i] = acc[u][v];
-            else U[(j - nc) * ru + (i - nc)] = acc[u][v];
-          }
-        } else {
-          X[(int64_t)i * nc + j] = acc[u][v];
-        }
+      for (int v = 0; v < R; ++v) {
+        const int i = t.i0 + ra + 16 * u, j = t.j0 + cb + 16 * v;
+        if (i < imax && j < jmax && i >= j) F[(int64_t)j * m + i] = acc[u][v];
       }
-    }
+  } else if (reg == 2) {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) {
+        const int i = t.i0 + ra + 16 * u, j = t.j0 + cb + 16 * v;
+        if (i < imax && j < jmax && i >= j) U[(j - nc) * ru + (i - nc)] = acc[u][v];
+      }
+  } else {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+      for (int v = 0; v < R; ++v) {
+        const int i = t.i0 + ra + 16 * u, j = t.j0 + cb + 16 * v;
+        if (i < imax && j < jmax) X[(int64_t)i * nc + j] = acc[u][v];
+      }
   }
 }
 
@@ -415,22 +455,42 @@ __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, int64_t 
   }
 }
 
-// panel G (m x nc column-major) from X and 1/d; fronts of the level by
-// blockIdx.y (stride gridDim.y)
+// panel G (m x nc column-major) from X (row-major) and 1/d: 64 x 64 tiles
+// transposed through LDS, so that both the reads of X and the writes of G
+// are coalesced; fronts of the level by blockIdx.y (stride gridDim.y), tiles
+// of a front by blockIdx.x (stride gridDim.x)
+constexpr int kEmitTile = 64;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_t *sn, int nf,
                                                  const double *base, const int32_t *rows,
                                                  T *panels, T *dinv) {
+  constexpr int E = kEmitTile, RP = 256 / E;  // rows (columns) per pass
+  __shared__ double tile[E][E + 1];
+  const int c = threadIdx.x % E, rq = threadIdx.x / E;
   for (int q = blockIdx.y; q < nf; q += gridDim.y) {
     const GfFront f = fr[sn[q]];
-    const int64_t total = (int64_t)f.m * f.nc;
+    const int m = f.m, nc = f.nc;
+    const int ti = (m + E - 1) / E, tj = (nc + E - 1) / E;
     const double *X = base + f.offX;
     T *G = panels + f.panel_off;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-      const int i = (int)(idx % f.m), j = (int)(idx / f.m);
-      const double x = X[(int64_t)i * f.nc + j];
-      G[idx] = (T)(i < f.nc ? x : -x);
+    for (int t = blockIdx.x; t < ti * tj; t += gridDim.x) {
+      const int i0 = (t % ti) * E, j0 = (t / ti) * E;
+      const int jc = min(j0 + c, nc - 1);
+      double v[E / RP];
+#pragma unroll
+      for (int u = 0; u < E / RP; ++u) v[u] = X[(int64_t)min(i0 + rq + RP * u, m - 1) * nc + jc];
+      __syncthreads();  // the previous tile's reads of LDS are done
+#pragma unroll
+      for (int u = 0; u < E / RP; ++u) tile[rq + RP * u][c] = v[u];
+      __syncthreads();
+      const int i = i0 + c;
+#pragma unroll
+      for (int u = 0; u < E / RP; ++u) {
+        const int j = j0 + rq + RP * u;
+        const double x = tile[c][rq + RP * u];
+        if (i < m && j < nc) G[(int64_t)j * m + i] = (T)(i < nc ? x : -x);
+      }
     }
     if (blockIdx.x == 0) {
       const int32_t *rw = rows + f.rows_off;
@@ -499,12 +559,13 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
     if (nh > 0) k_gf_update<<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
-    int64_t maxe = 0;
+    int64_t maxt = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];
-      maxe = std::max<int64_t>(maxe, (int64_t)g.m * g.nc);
+      maxt = std::max<int64_t>(maxt, (int64_t)((g.m + kEmitTile - 1) / kEmitTile) *
+                                         ((g.nc + kEmitTile - 1) / kEmitTile));
     }
-    const int64_t gx = std::min<int64_t>((maxe + 255) / 256, 1024);
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(maxt, 1024));
     k_gf_emit<T><<<grid2(gx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts, d.rows, panels,
                                                 dinv);
   }

@@ -159,8 +159,6 @@ void launch_dot(hipStream_t st, int64_t n, const double *a, const double *b, dou
                 const PcgState *state);
 void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int first);
 void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np);
-void launch_update_xr(hipStream_t st, int64_t n, double *x, double *r, const double *p,
-                      const double *q, double *part_rr, const PcgState *state);
 void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np);
 void launch_update_p(hipStream_t st, int64_t n, double *p, const double *z, const PcgState *state,
                      int first);

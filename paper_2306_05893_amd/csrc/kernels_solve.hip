@@ -165,23 +165,6 @@ __global__ __launch_bounds__(kBlock) void k_ctl_alpha(PcgState *s, const double 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_xr(int64_t n, double *x, double *r,
-                                                      const double *p, const double *q,
-                                                      double *part, const PcgState *s) {
-  if (s->done) return;
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const double al = s->alpha;
-  double rr = 0.0;
-  if (i < n) {
-    x[i] += al * p[i];
-    const double ri = r[i] - al * q[i];
-    r[i] = ri;
-    rr = ri * ri;
-  }
-  rr = block_sum(rr);
-  if (threadIdx.x == 0) part[blockIdx.x] = rr;
-}
-
 __global__ __launch_bounds__(kBlock) void k_ctl_rr(PcgState *s, const double *part, int np) {
   if (s->done) return;
   const double rr = sum_parts(part, np);
@@ -486,10 +469,6 @@ void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int 
 }
 void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np) {
   k_ctl_alpha<<<1, kBlock, 0, st>>>(s, part, np);
-}
-void launch_update_xr(hipStream_t st, int64_t n, double *x, double *r, const double *p,
-                      const double *q, double *part, const PcgState *state) {
-  k_update_xr<<<cg_blocks(n), kBlock, 0, st>>>(n, x, r, p, q, part, state);
 }
 void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np) {
   k_ctl_rr<<<1, kBlock, 0, st>>>(s, part, np);

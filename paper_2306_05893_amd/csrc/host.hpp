@@ -185,7 +185,9 @@ struct GfPlan {
   std::vector<int32_t> rel;                  // child struct row -> parent front row
   std::vector<int64_t> rel_off;              // by supernode, into rel
   std::vector<GfExt> ext;                    // extend-add tiles, by parent level
-  std::vector<int64_t> ext_ptr;
+  std::vector<int64_t> ext_ptr;              //   and child rank: ext_pass bounds the
+  std::vector<int64_t> ext_pass;             //   passes, ext_lvl_pass[L] is level L's
+  std::vector<int32_t> ext_lvl_pass;         //   first pass (one child per parent)
   std::vector<int32_t> step_k0;              // panel steps: k0 of each step
   std::vector<int32_t> step_level;           // level of each step
   std::vector<int32_t> panel_sn;             // fronts with nc > k0, per step

@@ -111,6 +111,8 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
 
   G.a_ptr.assign(1, 0);
   G.ext_ptr.assign(1, 0);
+  G.ext_pass.assign(1, 0);
+  G.ext_lvl_pass.clear();
   G.lvl_step_ptr.assign(1, 0);
   G.panel_ptr.assign(1, 0);
   double flops = 0.0;
@@ -133,13 +135,23 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
       for (int32_t i = 0; i < sn.m; ++i) pos[rw[i]] = -1;
     }
     G.a_ptr.push_back((int64_t)G.a_csr.size());
-    // extend-add tiles of the children of this level's fronts
-    for (int32_t s : by_level[L])
-      for (int32_t c : S.children[s]) {
+    // extend-add tiles of the children of this level's fronts, one pass per
+    // child rank: within a pass every parent receives from one child only,
+    // and a child's update block maps one to one into its parent's front, so
+    // no two tiles of a pass add into the same entry
+    G.ext_lvl_pass.push_back((int32_t)G.ext_pass.size() - 1);
+    size_t maxch = 0;
+    for (int32_t s : by_level[L]) maxch = std::max(maxch, S.children[s].size());
+    for (size_t rank = 0; rank < maxch; ++rank) {
+      for (int32_t s : by_level[L]) {
+        if (rank >= S.children[s].size()) continue;
+        const int32_t c = S.children[s][rank];
         const int32_t nr = S.sn[c].m - S.sn[c].nc;
         for (int32_t j0 = 0; j0 < nr; j0 += 32)
           for (int32_t i0 = j0; i0 < nr; i0 += 32) G.ext.push_back({c, i0, j0, 0});
       }
+      G.ext_pass.push_back((int64_t)G.ext.size());
+    }
     G.ext_ptr.push_back((int64_t)G.ext.size());
     // panel steps
     int32_t maxnc = 0;

@@ -63,9 +63,13 @@ __global__ void k_gf_scatter(int64_t n, const int32_t *a_csr, const int64_t *a_o
 }
 
 // extend-add: 32 x 32 tiles of the children's update matrices (tile per
-// block, stride gridDim.x).  Thread (tx, ty) adds entries (i0 + tx,
-// j0 + ty + 8q), q < 4, of the lower triangle; the four loads of each kind
-// are clamped into the block and issued together before the atomics.
+// block, stride gridDim.x), one launch per child rank.  Within a launch every
+// parent receives from one child and the child's rows map one to one into
+// the parent's, so each target entry is added by one thread: plain
+// read-add-write, coalesced along the rows, instead of atomics.  Thread
+// (tx, ty) adds entries (i0 + tx, j0 + ty + 8q), q < 4, of the lower
+// triangle; the four loads of each kind are clamped into the block and issued
+// together before the adds.
 __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *__restrict__ ext, int64_t n_ext,
                                                    const GfFront *__restrict__ fr,
                                                    const int32_t *__restrict__ parent,
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void k_gf_extend(const GfExt *__restrict__ ext
       // own columns of the parent, or its update block
       const int64_t o = lo < fp.nc ? fp.offF + (int64_t)lo * fp.m + hi
                                    : fp.offU + (int64_t)(lo - fp.nc) * rp + (hi - fp.nc);
-      atomicAdd(base + o, u[q]);
+      base[o] += u[q];
     }
   }
 }
@@ -530,10 +534,13 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
     if (na > 0)
       k_gf_scatter<TA><<<grid1((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0, A,
                                                                  d.fronts);
-    const int64_t e0 = P.ext_ptr[L], ne = P.ext_ptr[L + 1] - e0;
-    if (ne > 0)
-      k_gf_extend<<<grid1(ne), 256, 0, st>>>(d.ext + e0, ne, d.fr, d.parent, d.rel, d.rel_off,
-                                             d.fronts);
+    const int p_end = L + 1 < nl ? P.ext_lvl_pass[L + 1] : (int)P.ext_pass.size() - 1;
+    for (int pass = P.ext_lvl_pass[L]; pass < p_end; ++pass) {
+      const int64_t e0 = P.ext_pass[pass], ne = P.ext_pass[pass + 1] - e0;
+      if (ne > 0)
+        k_gf_extend<<<grid1(ne), 256, 0, st>>>(d.ext + e0, ne, d.fr, d.parent, d.rel, d.rel_off,
+                                               d.fronts);
+    }
     for (int s = P.lvl_step_ptr[L]; s < P.lvl_step_ptr[L + 1]; ++s) {
       const int k0 = P.step_k0[s];
       const int64_t p0 = P.panel_ptr[s], np = P.panel_ptr[s + 1] - p0;

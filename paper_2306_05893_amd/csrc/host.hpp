@@ -157,8 +157,9 @@ struct GfFront {
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
   int64_t panel_off;   // output panel offset, as Supernode::panel_off
 };
-// kGfTile x kGfTile output tile of an update (L: the front's scaled lower
-// factor, d: its pivots, W = L D for the current panel, X: augmented block):
+// Square output tile of an update, kGfStepTile (regions 0/1) or kGfTile
+// (regions 2/3) wide (L: the front's scaled lower factor, d: its pivots,
+// W = L D for the current panel, X: augmented block):
 //   region 0  F[i, j] -= sum_{k in panel} L[i, k] W[j, k]   k1 <= j < nc, i >= j
 //   region 1  X[i, j] -= sum_{k in panel} L[i, k] X[k, j]   k1 <= i < nc, j < k1
 //   region 2  F[i, j] -= sum_{k < nc} L[i, k] d_k L[j, k]   nc <= j <= i (Schur)
@@ -171,7 +172,9 @@ struct GfExt {         // 32 x 32 tile of a child's update matrix (extend-add)
   int32_t child, i0, j0, pad;
 };
 constexpr int kGfPanel = 64;   // panel width of the GPU factorisation
-constexpr int kGfTile = 128;   // trailing-update tile
+constexpr int kGfTile = 128;   // trailing-update tile (Schur complements)
+constexpr int kGfStepTile = 64; // update tile of the panel steps (K = 64:
+                                // smaller tiles, more of them in flight)
 
 struct GfPlan {
   std::vector<GfFront> fr;                   // by supernode

@@ -168,10 +168,10 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
         const int32_t kb = k1 - k0;
         // the rest of the own columns (all rows below the diagonal) and the
         // own rows of X; the Schur complement waits for the level's end
-        for (int32_t j0 = k1; j0 < sn.nc; j0 += kGfTile)
-          for (int32_t i0 = j0; i0 < sn.m; i0 += kGfTile) G.upd.push_back({s, 0, i0, j0});
-        for (int32_t i0 = k1; i0 < sn.nc; i0 += kGfTile)
-          for (int32_t j0 = 0; j0 < k1; j0 += kGfTile) G.upd.push_back({s, 1, i0, j0});
+        for (int32_t j0 = k1; j0 < sn.nc; j0 += kGfStepTile)
+          for (int32_t i0 = j0; i0 < sn.m; i0 += kGfStepTile) G.upd.push_back({s, 0, i0, j0});
+        for (int32_t i0 = k1; i0 < sn.nc; i0 += kGfStepTile)
+          for (int32_t j0 = 0; j0 < k1; j0 += kGfStepTile) G.upd.push_back({s, 1, i0, j0});
         const double t = sn.nc - k1;
         flops += 2.0 * kb * (t * (sn.m - k1 - t / 2.0) + t * k1);
       }

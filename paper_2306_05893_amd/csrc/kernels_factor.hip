@@ -28,7 +28,6 @@ namespace fe {
 namespace {
 
 constexpr int NB = kGfPanel;
-constexpr int TL = kGfTile;
 
 // Start of a level: own columns and update block of F zeroed, X = [I; 0].
 // Fronts of the level by blockIdx.y (stride gridDim.y), grid-stride over the
@@ -304,10 +303,11 @@ __global__ __launch_bounds__(256) void k_gf_rowops(const GfFront *fr, const int3
   gf_rowops(fr[sn[blockIdx.y]], k0, (int)blockIdx.x, nrb, base);
 }
 
-// One 128 x 128 output tile of an update (regions as in GfTile; 8 x 8
+// One TL x TL output tile of an update (regions as in GfTile; TL/16 x TL/16
 // outputs per thread, loaded into the accumulators before the first stage).
 // The k range is staged through LDS 32 rows at a time: sA = L[i, k] (rows of
 // the tile), sB = W[j, k], d_k L[j, k] or X[k, j] (columns of the tile).
+template <int TL>
 __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base) {
   constexpr int KC = 32;
   const int m = f.m, nc = f.nc;
@@ -450,11 +450,12 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
 }
 
 // one tile per block (stride gridDim.x)
+template <int TL>
 __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, int64_t n_tiles,
                                                    const GfFront *fr, int k0, double *base) {
   for (int64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
     const GfTile t = tiles[q];
-    gf_update(t, fr[t.s], k0, base);
+    gf_update<TL>(t, fr[t.s], k0, base);
     __syncthreads();
   }
 }
@@ -562,10 +563,11 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
                         st>>>(d.fr, d.panel_sn + p0 + q0, k0, nrb, d.fronts);
       }
       const int64_t u0 = P.upd_lo[s], nu = P.upd_hi[s] - u0;
-      if (nu > 0) k_gf_update<<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);
+      if (nu > 0)
+        k_gf_update<kGfStepTile><<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
-    if (nh > 0) k_gf_update<<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
+    if (nh > 0) k_gf_update<kGfTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
     int64_t maxt = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];

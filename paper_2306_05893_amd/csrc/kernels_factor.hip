@@ -5,16 +5,17 @@
 //   init     zero the level's fronts; augmented block X = [I; 0]
 //   scatter  lower part of the own columns of A into the fronts
 //   extend   children's update matrices (the Schur complements left in the
-//            trailing part of their fronts) added into the parent fronts
+//            trailing part of their fronts) added into the parent fronts,
+//            one launch per child rank
 //   panels   for k0 = 0, 64, ...: one workgroup per front factors the
-//            64 x 64 diagonal block in LDS; then one launch applies the
-//            block to the rows below it (one thread per row, panel values
-//            in registers) and its row operations to the panel rows of X
-//            (one thread per column); then 128 x 128 FP64 FMA tiles update
-//            the remaining own columns of F and the own rows of X
+//            64 x 64 diagonal block in registers; then one launch applies
+//            the block to the rows below it (one thread per row, panel
+//            values in registers) and its row operations to the panel rows
+//            of X (one thread per column); then 64 x 64 FP64 FMA tiles
+//            update the remaining own columns of F and the own rows of X
 //   schur    once the own columns are done: the Schur complement
 //            F22 -= L21 D L21^T and the struct rows of X, -L21 X_own, in one
-//            pass over each output tile (K = nc)
+//            pass over each 128 x 128 output tile (K = nc)
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave

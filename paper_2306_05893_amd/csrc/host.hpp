@@ -175,6 +175,8 @@ constexpr int kGfPanel = 64;   // panel width of the GPU factorisation
 constexpr int kGfTile = 128;   // trailing-update tile (Schur complements)
 constexpr int kGfStepTile = 64; // update tile of the panel steps (K = 64:
                                 // smaller tiles, more of them in flight)
+constexpr int kGfSchurMinTiles = 1024;  // fewer large Schur tiles than this
+                                        // in a level: the level uses 64-wide
 
 struct GfPlan {
   std::vector<GfFront> fr;                   // by supernode
@@ -198,6 +200,7 @@ struct GfPlan {
   std::vector<GfTile> upd;                   // update tiles (regions 0-3)
   std::vector<int64_t> upd_lo, upd_hi;       // regions 0/1 of each step
   std::vector<int64_t> schur_lo, schur_hi;   // regions 2/3 of each level
+  std::vector<int32_t> schur_tile;           // their tile width (per level)
   std::vector<int32_t> lvl_step_ptr;         // steps of each level
   double flops = 0.0;
 };

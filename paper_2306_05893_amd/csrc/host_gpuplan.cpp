@@ -178,14 +178,26 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
       G.panel_ptr.push_back((int64_t)G.panel_sn.size());
       G.upd_hi.push_back((int64_t)G.upd.size());
     }
-    // Schur complement and struct rows of X, one pass each (K = nc)
+    // Schur complement and struct rows of X, one pass each (K = nc), on
+    // kGfTile tiles, or kGfStepTile tiles when the level has too few of the
+    // large ones to fill the GPU
+    auto schur_tiles = [&](int32_t t) {
+      int64_t n = 0;
+      for (int32_t s : by_level[L]) {
+        const int64_t r = (S.sn[s].m - S.sn[s].nc + t - 1) / t, c = (S.sn[s].nc + t - 1) / t;
+        n += r * (r + 1) / 2 + r * c;
+      }
+      return n;
+    };
+    const int32_t st = schur_tiles(kGfTile) >= kGfSchurMinTiles ? kGfTile : kGfStepTile;
+    G.schur_tile.push_back(st);
     G.schur_lo.push_back((int64_t)G.upd.size());
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
-      for (int32_t j0 = sn.nc; j0 < sn.m; j0 += kGfTile)
-        for (int32_t i0 = j0; i0 < sn.m; i0 += kGfTile) G.upd.push_back({s, 2, i0, j0});
-      for (int32_t i0 = sn.nc; i0 < sn.m; i0 += kGfTile)
-        for (int32_t j0 = 0; j0 < sn.nc; j0 += kGfTile) G.upd.push_back({s, 3, i0, j0});
+      for (int32_t j0 = sn.nc; j0 < sn.m; j0 += st)
+        for (int32_t i0 = j0; i0 < sn.m; i0 += st) G.upd.push_back({s, 2, i0, j0});
+      for (int32_t i0 = sn.nc; i0 < sn.m; i0 += st)
+        for (int32_t j0 = 0; j0 < sn.nc; j0 += st) G.upd.push_back({s, 3, i0, j0});
       const double r = sn.m - sn.nc, c = sn.nc;
       flops += r * r * c + r * c * c;
     }

@@ -15,7 +15,8 @@
 //            update the remaining own columns of F and the own rows of X
 //   schur    once the own columns are done: the Schur complement
 //            F22 -= L21 D L21^T and the struct rows of X, -L21 X_own, in one
-//            pass over each 128 x 128 output tile (K = nc)
+//            pass over each 128 x 128 output tile (K = nc; 64 x 64 on the
+//            levels with too few large tiles to fill the GPU)
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave
@@ -568,7 +569,10 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
         k_gf_update<kGfStepTile><<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
-    if (nh > 0) k_gf_update<kGfTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
+    if (nh > 0 && P.schur_tile[L] == kGfTile)
+      k_gf_update<kGfTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
+    else if (nh > 0)
+      k_gf_update<kGfStepTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
     int64_t maxt = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];

@@ -4,7 +4,8 @@ fixed (one free node), a hex with every DOF fixed (A = I, b = 0, nothing
 moves, no CG iteration) and a free-floating block with no Dirichlet DOF at
 all (A is positive definite through the mass term alone).  Each runs two
 steps in FP64 and in mixed precision, with a fresh factor every step, on
-the host-thread factorisation and on the GPU one."""
+the host-thread factorisation and on the GPU one.  The CG's error paths
+(an indefinite matrix, an iteration cap) on the tet beam."""
 import dataclasses
 
 import numpy as np
@@ -12,7 +13,7 @@ import pytest
 import torch
 
 import synth
-from oracle import step
+from oracle import assembly, step
 
 pytestmark = pytest.mark.gpu
 
@@ -81,4 +82,48 @@ def test_degenerate_mesh_steps(kind, prec, gpu_factor):
             # trajectory tests
             tol = 1e-9 if prec == 0 else 1e-4
             assert eq <= tol and ev <= tol
+    ctx.close()
+
+
+def _tet_beam_system(prec):
+    w = synth.make("tet_beam")
+    ref = step.assemble(w, w.q0(), w.v0())
+    ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec=prec, device=DEV)
+    A = torch.as_tensor(ref.vals, dtype=ctx.value_dtype, device=DEV)
+    return ref, ctx, A
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cg_reports_indefinite(prec):
+    """-A (negative definite, Jacobi preconditioner): the first p^T A p is
+    negative, and the solve stops with FE_EINDEF."""
+    from paper_2306_05893_amd import _lib
+    print(f"[cg-errors] indefinite prec={prec}", flush=True)
+    ref, ctx, A = _tet_beam_system(prec)
+    with pytest.raises(_lib.FEError) as ei:
+        ctx.pcg_solve(-A, _t(ref.b), rel_tol=1e-10, max_it=50)
+    assert ei.value.code == _lib.FE_EINDEF
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_cg_reports_not_converged(prec):
+    """An iteration cap far below what the tolerance needs: FE_ENOTCONV, the
+    iterate and the recomputed residual still returned."""
+    from paper_2306_05893_amd import _lib
+    print(f"[cg-errors] not converged prec={prec}", flush=True)
+    ref, ctx, A = _tet_beam_system(prec)
+    x, st = ctx.pcg_solve(A, _t(ref.b), rel_tol=1e-14, max_it=4)
+    assert st.status == _lib.FE_ENOTCONV
+    assert 4 <= st.iterations <= 6
+    xh = x.cpu().numpy()
+    assert np.isfinite(xh).all()
+    # the reported residual is the recomputed one: FP64 arithmetic on the
+    # context's values (FP32-rounded in mixed precision)
+    vals = ref.vals if prec == 0 else ref.vals.astype(np.float32).astype(np.float64)
+    p = ref.pat
+    res = np.linalg.norm(ref.b - assembly.csr_matvec(p.row_ptr, p.col_idx, vals, xh))
+    res /= np.linalg.norm(ref.b)
+    print(f"  iterations {st.iterations}, rel-res {st.rel_res:.3e} (oracle {res:.3e})")
+    assert res > 1e-14 and abs(st.rel_res - res) <= 1e-8 * res
     ctx.close()

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_gf_diag(const GfFront *fr, const int32_
 // diagonal block, already factored, staged in LDS):
 //  * blockIdx.x < nrb: rows below the block, one thread per row with the kb
 //    panel values in registers:
-//      f_k <- f_k - sum_{c<k} l_c L_d[k][c],  W[i, k] = f_k,  l_k = f_k / d_k;
+//      f_k <- f_k - sum_{c<k} f_c L_d[k][c],  W[i, k] = f_k,  l_k = f_k / d_k;
 //  * otherwise: columns c < k1 of the panel rows of X, one thread per
 //    column, forward substitution with the unit lower factor of the block:
 //      x_r <- x_r - sum_{k<r} L_d[r][k] x_k.

@@ -137,3 +137,17 @@ def test_query_workspace_grows_with_precision():
     s32 = ctx.query(1)
     s64 = ctx.query(0)
     assert s64.ws_bytes > s32.ws_bytes > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark is single-GPU: any --gpus above 1 exits with status 2
+    # and a message before any GPU work (so this runs without a GPU)
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for extra in ([], ["--factor-only", "1"], ["--kernel-pass-only"]):
+        p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", *extra],
+                           stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
+        assert p.returncode == 2, (extra, p.stderr[-300:])
+        assert "one GPU only" in p.stderr
+        assert p.stdout == ""

@@ -32,10 +32,14 @@
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Calls on one context are not re-entrant; use one context per stream.
  * - Precision: FE_PREC_FP64 computes everything in FP64.  FE_PREC_MIXED
- *   stores A and the factor panels in FP32 and runs element arithmetic, the
- *   SpMV products and the triangular solves in FP32, while state, CG vectors,
- *   dot products, alpha/beta, the SpMV row sums and the residual check stay
- *   FP64; the LDL^T factorisation itself is always FP64 on the host.
+ *   stores A and the factor panels in FP32 and runs the element arithmetic
+ *   and the triangular solves in FP32; the SpMV reads the FP32 values of A
+ *   and upcasts them exactly, so its products and row sums are FP64, as are
+ *   state, CG vectors, dot products, alpha/beta and the residual check.  The
+ *   LDL^T factorisation itself is always FP64, on the GPU (its own stream;
+ *   fe_build_opts.factor_on_gpu = 1) or on the host factor thread, and its
+ *   panels are rounded to FP32 once when they are written.  The adjoint
+ *   element pass of fe_step_adjoint is FP64 in both modes.
  */
 #ifndef FE_H
 #define FE_H
@@ -213,9 +217,14 @@ int fe_assemble(fe_ctx *ctx, const fe_params *params, const double *q,
                 const double *v, void *A_vals, double *b, void *stream);
 
 /* Snapshot A (device, the context's precision) after the work queued on
- * `stream`, and factor it as P = L D L^T in FP64 on the host factor thread
- * (Sec. 3.3).  Returns at once.  `tag` labels the factor (usually the step
- * index).  FE_EBUSY if a previous job has not finished. */
+ * `stream`, and factor it as P = L D L^T in FP64 (Sec. 3.3): on the GPU, on
+ * the context's own factorisation stream, when the context was built with
+ * factor_on_gpu = 1 (the result is written straight into the idle factor
+ * slot), else on the host factor thread (the snapshot is copied to pinned
+ * host memory first).  Work queued on `stream` after this call waits for
+ * the snapshot copy, so A may be overwritten by the next assembly at once.
+ * Returns without waiting for the factorisation.  `tag` labels the factor
+ * (usually the step index).  FE_EBUSY if a previous job has not finished. */
 int fe_factor_async(fe_ctx *ctx, const void *A_vals, int64_t tag, void *stream);
 
 /* Newest finished factor's tag (-1 if none) and the status of the last job. */

@@ -570,17 +570,22 @@ int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_i
     launch_update_p(st, n, c->d_p, c->d_z, c->d_state, 1);
   };
   restart();
-  int chunk = 2;
+  int chunk = std::min(2, max_it);
   int status = FE_OK;
   int restarts = 0;
   int32_t last_it = -1;
   for (;;) {
     hipGraphExec_t g = c->use_graphs && !c->timing ? iter_graph<T>(c, A, x) : nullptr;
     if (g) {
-      for (int k = 0; k < chunk; k += kGraphIters) {
+      // whole graphs, then the remainder of the chunk (at most
+      // kGraphIters - 1 iterations) as eager launches, so that no batch runs
+      // past max_it
+      int k = 0;
+      for (; k + kGraphIters <= chunk; k += kGraphIters) {
         hipError_t e = hipGraphLaunch(g, st);
         if (e != hipSuccess) return c->fail(FE_EDEVICE, "graph launch: %s", hipGetErrorString(e));
       }
+      for (; k < chunk; ++k) cg_iteration<T>(c, A, x, st);
     } else {
       for (int k = 0; k < chunk; ++k) cg_iteration<T>(c, A, x, st);
     }
@@ -630,7 +635,6 @@ int pcg(fe_ctx *c, const T *A, const double *b, double *x, double tol, int max_i
     chunk = std::min(16, std::max(2, chunk * 2));
     chunk = std::min(chunk, max_it - h.it);
     if (chunk <= 0) chunk = 1;
-    chunk = (chunk + kGraphIters - 1) / kGraphIters * kGraphIters;
   }
   if (out) {
     out->iterations = c->h_state->it;
@@ -749,7 +753,8 @@ int install_locked(fe_ctx *c, hipStream_t st) {
   return FE_OK;
 }
 
-// GPU job: snapshot A on the factor stream (after the work queued on st),
+// GPU job: snapshot A on the factor stream (after the work queued on st;
+// later work on st, which may assemble into the same A, waits for the copy),
 // then factor into the idle slot once the solves that used it are done.
 int gf_start_locked(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   const int slot = c->active_slot < 0 ? 0 : 1 - c->active_slot;
@@ -757,9 +762,11 @@ int gf_start_locked(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   c->ready_slot = -1;
   HIP_TRY(hipEventRecord(c->ev_snap_ready, st));
   HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_snap_ready, 0));
-  HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_slot_free[slot], 0));
   HIP_TRY(hipMemcpyAsync(c->d_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToDevice,
                          c->factor_stream));
+  HIP_TRY(hipEventRecord(c->ev_snap_done, c->factor_stream));
+  HIP_TRY(hipStreamWaitEvent(st, c->ev_snap_done, 0));
+  HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_slot_free[slot], 0));
   HIP_TRY(hipMemsetAsync(c->gd.status, 0, sizeof(int), c->factor_stream));
   if (c->prec == FE_PREC_MIXED)
     launch_gpu_factor<float, float>(c->factor_stream, c->G, c->gd, (const float *)c->d_Asnap,
@@ -784,6 +791,8 @@ int factor_async_impl(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(c->h_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToHost,
                          c->copy_stream));
   HIP_TRY(hipEventRecord(c->ev_snap_done, c->copy_stream));
+  // later work on st may overwrite A (the next assembly): it waits for the copy
+  HIP_TRY(hipStreamWaitEvent(st, c->ev_snap_done, 0));
   c->job_tag = tag;
   c->job_pending = true;
   c->cv.notify_all();

@@ -16,6 +16,9 @@
 //    dP[W]    = W S + F S(sym(F^T W))
 //    d2P[W,U] = W S(sym(F^T U)) + U S(sym(F^T W)) + F S(sym(U^T W))
 // One thread per element; results are scattered with FP64 atomics.
+// The element arithmetic is FP64 in both precision modes: the pass runs once
+// per reverse step beside a whole CG solve, so its cost is small, and the
+// third-derivative terms then carry no FP32 rounding into dL/dE.
 #include "device.hpp"
 
 namespace fe {
@@ -110,12 +113,27 @@ __device__ inline void point_terms(const Mat3<T> &H, const Mat3<T> &Mu, const Ma
   F(1, 1) += T(1);
   F(2, 2) += T(1);
   if (MAT == 0) {
-    const T J = det3(F);
-    const Mat3<T> B = inv3(F, J);
+    // J - 1 from the invariants of H (det(I + H) = 1 + tr H + (tr^2 H -
+    // tr H^2) / 2 + det H) and P = F^{-T} (2 mu E + lam lnJ I) with
+    // E = (H + H^T + H^T H) / 2: near rest neither cancels the O(1) parts
+    // of F and F^{-T} against each other.
+    const T trH = trace(H);
+    const Mat3<T> HH = mul(H, H);
+    const T Jm1 = trH + T(0.5) * (trH * trH - trace(HH)) + det3(H);
+    const Mat3<T> B = inv3(F, T(1) + Jm1);
     const Mat3<T> BT = tr_(B);
-    const T lnJ = log(J);
+    const T lnJ = log1p(Jm1);
     const T c = lam * lnJ - mu;
-    for (int i = 0; i < 9; ++i) P.m[i] = mu * F.m[i] + c * BT.m[i];
+    {
+      Mat3<T> S;
+      const Mat3<T> HtH = mul(tr_(H), H);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S(i, j) = mu * (H(i, j) + H(j, i) + HtH(i, j));
+      S(0, 0) += lam * lnJ;
+      S(1, 1) += lam * lnJ;
+      S(2, 2) += lam * lnJ;
+      P = mul(BT, S);
+    }
     const Mat3<T> Wh = mul(B, Mu), Uh = mul(B, V);
     const Mat3<T> WhB = tr_(mul(Wh, B)), UhB = tr_(mul(Uh, B));
     const T trW = trace(Wh), trU = trace(Uh);
@@ -292,7 +310,7 @@ void launch_adjoint_element(hipStream_t st, int elem_type, int64_t n_elems, cons
   if (n_elems <= 0) return;
   const unsigned blocks = (unsigned)((n_elems + 127) / 128);
 #define FE_ADJ(MAT, NEN)                                                                   \
-  k_adjoint_elem<T, MAT, NEN><<<blocks, 128, 0, st>>>(n_elems, conn, X, q, mu, vnp1, E, prm, \
+  k_adjoint_elem<double, MAT, NEN><<<blocks, 128, 0, st>>>(n_elems, conn, X, q, mu, vnp1, E, prm, \
                                                       Kmu, Mmu, Tmv, dE)
   if (elem_type == 8) {
     if (prm.material == 0) FE_ADJ(0, 8); else FE_ADJ(1, 8);

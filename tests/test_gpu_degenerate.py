@@ -106,16 +106,18 @@ def test_cg_reports_indefinite(prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_cg_reports_not_converged(prec):
-    """An iteration cap far below what the tolerance needs: FE_ENOTCONV, the
-    iterate and the recomputed residual still returned."""
+@pytest.mark.parametrize("prec,max_it", [(0, 4), (1, 4), (0, 5), (1, 7)])
+def test_cg_reports_not_converged(prec, max_it):
+    """An iteration cap far below what the tolerance needs: FE_ENOTCONV after
+    exactly max_it iterations (odd caps too: the graph-captured batches of
+    two iterations must not overshoot), the iterate and the recomputed
+    residual still returned."""
     from paper_2306_05893_amd import _lib
-    print(f"[cg-errors] not converged prec={prec}", flush=True)
+    print(f"[cg-errors] not converged prec={prec} max_it={max_it}", flush=True)
     ref, ctx, A = _tet_beam_system(prec)
-    x, st = ctx.pcg_solve(A, _t(ref.b), rel_tol=1e-14, max_it=4)
+    x, st = ctx.pcg_solve(A, _t(ref.b), rel_tol=1e-14, max_it=max_it)
     assert st.status == _lib.FE_ENOTCONV
-    assert 4 <= st.iterations <= 6
+    assert st.iterations == max_it
     xh = x.cpu().numpy()
     assert np.isfinite(xh).all()
     # the reported residual is the recomputed one: FP64 arithmetic on the

@@ -5,8 +5,9 @@ b against the oracle's complete assembly; SpMV against the oracle's CSR
 product; one step with a fresh factor against the oracle's banded-Cholesky
 step; preconditioner residual; a short run of the benchmark schedule with a
 residual certificate at every step.
-tet_block (206,763 DOFs, jittered Kuhn tets, neo-Hookean, mixed): assembly
-parity and the residual certificate of one preconditioned solve.
+tet_block (206,763 DOFs, jittered Kuhn tets, neo-Hookean), mixed and FP64:
+assembly parity and the residual certificate of one step with a fresh
+factor.
 """
 import numpy as np
 import pytest
@@ -105,24 +106,46 @@ def test_hex_beam_benchmark_schedule(hex_beam):
     sim.ctx.close()
 
 
-def test_tet_block_assembly_and_solve():
+@pytest.fixture(scope="module")
+def tet_block():
     w = synth.make("tet_block")
-    sim = Simulation(w, prec=1)
-    ctx = sim.ctx
-    print("[fullsize] tet_block oracle", flush=True)
+    print("[fullsize] tet_block oracle pattern and assembly at rest", flush=True)
     pat = step.pattern(w)
     ref = step.assemble(w, w.q0(), w.v0(), pat=pat)
+    return w, pat, ref
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tet_block_assembly_and_solve(tet_block, prec):
+    """Assembly parity at rest, then one step from rest with a fresh factor
+    (refresh 1, lag 0): the acceleration's residual is recomputed by the
+    oracle's CSR product with the GPU's own A (FP32-valued in mixed
+    precision) and with the oracle's exact A."""
+    w, pat, ref = tet_block
+    print(f"[fullsize] tet_block prec={prec}", flush=True)
+    sim = Simulation(w, prec=prec, factor_on_gpu=True)
+    ctx = sim.ctx
     A, b = ctx.assemble(sim.params, sim.q, sim.v)
     torch.cuda.synchronize()
     Ag = A.double().cpu().numpy()
-    ea, eb = _rel(Ag, ref.vals), _rel(b.cpu().numpy(), ref.b)
+    bg = b.cpu().numpy()
+    ea, eb = _rel(Ag, ref.vals), _rel(bg, ref.b)
     print(f"  A err {ea:.2e} b err {eb:.2e}")
-    assert ea <= 1e-5 and eb <= 1e-5
-    ctx.factorize_now(A, 0)
-    x, st = ctx.pcg_solve(A, b, rel_tol=1e-8, max_it=200)
-    xg = x.cpu().numpy()
-    res = np.linalg.norm(b.cpu().numpy() - assembly.csr_matvec(pat.row_ptr, pat.col_idx, Ag, xg)) / \
-        np.linalg.norm(b.cpu().numpy())
-    print(f"  it={st.iterations} rel_res={st.rel_res:.2e} oracle-recomputed {res:.2e}")
-    assert res <= 1e-8 * 1.01 and st.iterations <= 3
+    tol = 1e-5 if prec == 1 else 1e-12
+    assert ea <= tol and eb <= tol
+    a = torch.zeros_like(sim.q)
+    st = sim.step(sim.opts(rel_tol=1e-8, max_it=200, refresh=1, lag=0,
+                           mode=FE_FACTOR_DETERMINISTIC), a_out=a)
+    torch.cuda.synchronize()
+    ah = a.cpu().numpy()
+    res = np.linalg.norm(bg - assembly.csr_matvec(pat.row_ptr, pat.col_idx, Ag, ah)) / \
+        np.linalg.norm(bg)
+    res_exact = np.linalg.norm(ref.b - assembly.csr_matvec(pat.row_ptr, pat.col_idx, ref.vals,
+                                                           ah)) / np.linalg.norm(ref.b)
+    print(f"  it={st.solve.iterations} rel_res={st.solve.rel_res:.2e} oracle-recomputed "
+          f"{res:.2e} (vs the oracle's A {res_exact:.2e})")
+    assert st.solve.status == 0 and st.solve.iterations <= 3
+    assert res <= 1e-8 * 1.01
+    if prec == 0:
+        assert res_exact <= 1e-8 * 1.01
     ctx.close()

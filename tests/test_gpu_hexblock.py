@@ -10,7 +10,10 @@ sampled and the rest is checked through properties that hold at any size:
   complete in that sub-mesh): columns bit-exact, values within FP32 rounding;
 * SpMV against a host CSR product with the same values;
 * one preconditioned solve with a fresh GPU factor, its residual recomputed
-  on the host in FP64.
+  on the host in FP64;
+* in FP64 (a context of its own): the sampled rows to 1e-12 and one step
+  with a fresh GPU factor whose acceleration meets rel-res 1e-8, recomputed
+  on the host.
 """
 import dataclasses
 import time
@@ -24,7 +27,7 @@ from oracle import assembly, step
 
 pytestmark = pytest.mark.gpu
 
-from paper_2306_05893_amd import FE_PREC_MIXED  # noqa: E402
+from paper_2306_05893_amd import FE_FACTOR_DETERMINISTIC, FE_PREC_FP64, FE_PREC_MIXED  # noqa: E402
 from paper_2306_05893_amd.sim import Simulation  # noqa: E402
 
 DEV = "cuda"
@@ -55,6 +58,10 @@ def block():
 
 def test_hex_block_sampled_rows(block):
     w, sim, q, v, A, b, rp, ci = block
+    _check_sampled_rows(w, q, v, A, b, rp, ci, 1e-5)
+
+
+def _check_sampled_rows(w, q, v, A, b, rp, ci, tol):
     rng = np.random.default_rng(5)
     free_nodes = np.flatnonzero(~w.fixed.reshape(-1, 3).any(axis=1))
     nodes = np.sort(rng.choice(free_nodes, 48, replace=False))
@@ -80,7 +87,7 @@ def test_hex_block_sampled_rows(block):
     # complete on the sampled rows, so the scale is taken from the GPU's b)
     eb = float(np.abs(bg[rows] - ref.b[rows]).max() / np.abs(bg).max())
     print(f"  sampled rows: A rel err {err_a / scale_a:.2e}  b rel err {eb:.2e}")
-    assert err_a / scale_a <= 1e-5 and eb <= 1e-5
+    assert err_a / scale_a <= tol and eb <= tol
 
 
 def test_hex_block_spmv(block):
@@ -107,3 +114,29 @@ def test_hex_block_solve_gpu_factor(block):
         np.linalg.norm(bg)
     print(f"  it={st.iterations} rel_res={st.rel_res:.2e} host-recomputed {res:.2e}")
     assert res <= 1e-8 * 1.01 and st.iterations <= 5
+
+
+def test_hex_block_fp64_step(block):
+    w, _, q, v, _, _, rp, ci = block
+    t0 = time.time()
+    sim = Simulation(w, prec=FE_PREC_FP64, factor_on_gpu=True)
+    A, b = sim.ctx.assemble(sim.params, _t(q), _t(v))
+    torch.cuda.synchronize()
+    print(f"[hexblock] FP64 context and assembly ({time.time() - t0:.1f}s)", flush=True)
+    _check_sampled_rows(w, q, v, A, b, rp, ci, 1e-12)
+    sim.q.copy_(_t(q))
+    sim.v.copy_(_t(v))
+    a = torch.zeros_like(sim.q)
+    t0 = time.time()
+    st = sim.step(sim.opts(rel_tol=1e-8, max_it=200, refresh=1, lag=0,
+                           mode=FE_FACTOR_DETERMINISTIC), a_out=a)
+    torch.cuda.synchronize()
+    print(f"[hexblock] FP64 step with a fresh factor ({time.time() - t0:.1f}s)", flush=True)
+    Ah = A.cpu().numpy()
+    bh = b.cpu().numpy()
+    res = np.linalg.norm(bh - assembly.csr_matvec(rp, ci, Ah, a.cpu().numpy())) / \
+        np.linalg.norm(bh)
+    print(f"  it={st.solve.iterations} rel_res={st.solve.rel_res:.2e} host-recomputed {res:.2e}")
+    assert st.solve.status == 0 and st.solve.iterations <= 5
+    assert res <= 1e-8 * 1.01
+    sim.ctx.close()

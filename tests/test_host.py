@@ -9,6 +9,7 @@
 * bad input is rejected with FE_EINVAL.
 """
 import ctypes as C
+import itertools
 import os
 import re
 
@@ -40,7 +41,8 @@ def test_library_exports_every_declared_symbol():
         assert name in _lib.SIGNATURES, name
 
 
-@pytest.mark.parametrize("mesh", ["tiny_tet", "tiny_hex", "tet_beam", "hex_diff"])
+@pytest.mark.parametrize("mesh", ["tiny_tet", "tiny_hex", "tet_beam", "hex_diff", "hex_beam",
+                                  "tet_block"])
 def test_pattern_and_map_bit_exact(mesh):
     w = synth.make(mesh)
     ctx = _ctx(w)
@@ -52,6 +54,41 @@ def test_pattern_and_map_bit_exact(mesh):
     assert ctx.sizes.compact_map == 1
     assert ctx.sizes.nnz == co.size
     assert ctx.sizes.map_len == tm.size
+
+
+def _hex_blocks(n):
+    """Node blocks of the trilinear-hex grid with n[i] nodes per axis: node
+    pairs within one cell, i.e. offsets in {-1, 0, 1} per axis."""
+    return int(np.prod([3 * k - 2 for k in n]))
+
+
+def _kuhn_blocks(n):
+    """Node blocks of the Kuhn (Freudenthal) tet grid: the node itself plus
+    both directions of every edge; the edges run along the seven offsets
+    d in {0, 1}^3 minus 0, each present prod(n_i - d_i) times."""
+    s = sum(int(np.prod([k - di for k, di in zip(n, d)]))
+            for d in itertools.product((0, 1), repeat=3) if any(d))
+    return int(np.prod(n)) + 2 * s
+
+
+@pytest.mark.parametrize("mesh", ["hex_beam", "tet_block", "hex_block"])
+def test_nnz_matches_closed_form_block_counts(mesh):
+    """Structural nonzeros at full size against closed forms of the grid: with
+    no fixed DOF, 9 per node block of the whole grid; with the z = 0 face fixed,
+    9 per node block of the free sub-grid (the nodes above z = 0) plus one
+    diagonal entry per fixed DOF."""
+    w = synth.make(mesh)
+    n = [d + 1 for d in w.dims]
+    blocks = _hex_blocks if w.elem_type == 8 else _kuhn_blocks
+    ctx = FEContext(w.X, w.conn, w.elem_type, None, device="cpu")
+    assert ctx.sizes.nnz == 9 * blocks(n)
+    ctx.close()
+    n_fixed = int(w.fixed.sum())
+    assert n_fixed == 3 * n[0] * n[1]
+    ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, device="cpu")
+    assert ctx.sizes.nnz == 9 * blocks([n[0], n[1], n[2] - 1]) + n_fixed
+    print(f"{mesh}: nnz {ctx.sizes.nnz} ({blocks(n)} node blocks without constraints)")
+    ctx.close()
 
 
 def test_pattern_per_dof_constraints_fall_back_to_int32_map():

@@ -528,6 +528,49 @@ def _factor_only(workload, n=5):
 
 
 
+def _age_curve(workload, nsteps, variants):
+    """CG iterations against the age of the factor, along the workload's own
+    trajectory: deterministic schedule with the workload's refresh period and
+    lag 0, so step kR + j solves with the factor of A_{kR} (age j).  One run
+    per variant (precision, warm start); per step: age, iterations, and the
+    wall time of the step (the blocking factorisation at each refresh is
+    included in that step's time)."""
+    import torch
+
+    import synth
+    from paper_2306_05893_amd import FE_FACTOR_DETERMINISTIC, FE_PREC_FP64, FE_PREC_MIXED
+    from paper_2306_05893_amd.sim import Simulation
+
+    w = synth.make(workload)
+    out = {"workload": workload, "n_dofs": w.n_dofs, "refresh": w.refresh, "steps": nsteps,
+           "variants": {}}
+    for tag in variants:
+        prec = FE_PREC_FP64 if tag.startswith("fp64") else FE_PREC_MIXED
+        warm = 1 if tag.endswith("warm") else 0
+        sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=True)
+        det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
+                       mode=FE_FACTOR_DETERMINISTIC, warm_start=warm)
+        ages, its, ms = [], [], []
+        for k in range(nsteps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.step(det)
+            torch.cuda.synchronize()
+            ms.append(round(1e3 * (time.perf_counter() - t0), 2))
+            ages.append(int(st.factor_lag))
+            its.append(int(st.solve.iterations))
+        _free(sim)
+        by_age = {}
+        for a, i in zip(ages, its):
+            by_age.setdefault(a, []).append(i)
+        out["variants"][tag] = {"age": ages, "iterations": its, "step_ms": ms,
+                                "mean_iterations_by_age": {a: round(sum(v) / len(v), 2)
+                                                           for a, v in sorted(by_age.items())}}
+        print(f"[bench] age curve {tag}: mean iterations {sum(its) / len(its):.1f}",
+              file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def _host_cores():
     """Cores this process may run on (what `nproc` reports) and the thread
     count the oracle's BLAS calls are given (capped by OMP_NUM_THREADS when
@@ -679,6 +722,10 @@ def main():
                     help="only run the contact measurements (compliance matrix, PGS)")
     ap.add_argument("--kernel-pass-only", action="store_true",
                     help="only the event-timed kernel pass (factor of A at rest)")
+    ap.add_argument("--age-curve", type=int, default=0, metavar="STEPS",
+                    help="only record CG iterations against factor age over STEPS steps of "
+                         "--workload (deterministic schedule; mixed, FP64, mixed with warm "
+                         "start)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
@@ -705,6 +752,9 @@ def main():
               flush=True)
     if args.factor_only > 0:
         _factor_only(args.workload, args.factor_only)
+        return
+    if args.age_curve > 0:
+        _age_curve(args.workload, args.age_curve, ("mixed", "fp64", "mixed_warm"))
         return
     if args.kernel_pass_only:
         _kernel_pass_only(args.workload, args.kernel_applies)

@@ -314,6 +314,27 @@ int fe_compliance(fe_ctx *ctx, int32_t k, const int32_t *h_row_ptr, const int32_
                   const double *h_val, int64_t nnz_h, double *W, double *Z, void *work,
                   int64_t work_bytes, void *stream);
 
+/* Bytes of the static device scratch of fe_compliance_noalloc (256 MiB). */
+#define FE_NOALLOC_SCRATCH_BYTES (256ll << 20)
+
+/* fe_compliance for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight real-time loops, harnesses that forbid
+ * hipMalloc): the same arguments and results without `work`.  The blocks of
+ * right-hand sides live in a static device array of FE_NOALLOC_SCRATCH_BYTES
+ * bytes, one per GPU, reserved when the first context is bound on that GPU
+ * (fe_bind) and held until the process ends; the call itself allocates
+ * nothing and clears the part of the array it uses before every use.  Every
+ * call on one GPU (any context, any stream) shares that array, so calls that
+ * overlap in time on one GPU race: the caller orders them (one stream, or
+ * events).  The caller still passes H, W and Z.  Synchronises `stream`.
+ * Errors: as fe_compliance; FE_ENOMEM when fe_multi_ws_bytes(k) exceeds
+ * FE_NOALLOC_SCRATCH_BYTES (e.g. k > 128 right-hand sides for 107,163 DOFs in
+ * mixed precision); FE_EDEVICE when the array's device address could not be
+ * obtained at fe_bind. */
+int fe_compliance_noalloc(fe_ctx *ctx, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                          const double *h_val, int64_t nnz_h, double *W, double *Z,
+                          void *stream);
+
 /* y = s_h op(H) x + s_y y_in with op(H) = H (transpose = 0: x device
  * [n_dofs], y and y_in device [k]) or H^T (transpose = 1: x device [k], y
  * and y_in device [n_dofs]); y_in NULL counts as zero and may alias y.

@@ -105,6 +105,7 @@ SIGNATURES = {
     "fe_precond_apply_multi": (C.c_int, [_P, _P, _P, C.c_int32, _P, C.c_int64, _P]),
     "fe_compliance": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, _P, _P, _P, C.c_int64,
                                 _P]),
+    "fe_compliance_noalloc": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, _P, _P, _P]),
     "fe_constraint_apply": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int64, C.c_int32,
                                       C.c_double, _P, C.c_double, _P, _P, _P]),
     "fe_pgs": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, C.c_double, _P, _P]),

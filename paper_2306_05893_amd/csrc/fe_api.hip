@@ -60,6 +60,36 @@ struct GraphKey {
 
 constexpr int kGraphIters = 2;  // CG iterations per captured graph
 
+// Static device scratch of fe_compliance_noalloc: the blocks of right-hand
+// sides live here instead of in a caller workspace.  One copy per GPU, held
+// from the first fe_bind on that GPU until the process ends.  In host code
+// `scratch` names a host-side shadow, not device memory: its device address
+// is looked up once per device with hipGetSymbolAddress and only that address
+// is passed to kernels.
+constexpr int64_t kScratchBytes = (int64_t)FE_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up on the
+// first call for that device).
+hipError_t scratch_address(int dev, void **out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct fe_ctx {
@@ -90,6 +120,8 @@ struct fe_ctx {
   MTile *d_mftiles = nullptr, *d_mbtiles = nullptr;  // many-right-hand-side sweeps
   int32_t *d_mbdofs = nullptr;                       // own DOFs per backward level
   int *d_herr = nullptr;                             // constraint-matrix index error flag
+  char *d_scratch = nullptr;  // device address of the static scratch (this device)
+  std::string scratch_err;    // why it is unavailable, if it is
   void *d_panels[2] = {nullptr, nullptr}, *d_dinv[2] = {nullptr, nullptr};
   double *d_jdinv = nullptr;
   double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_tmp = nullptr;
@@ -1084,6 +1116,16 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   if (((uintptr_t)d_ws) % 256 != 0) return c->fail(FE_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   HIP_TRY(hipGetDevice(&c->device));
+  {
+    void *sp = nullptr;
+    const hipError_t e = scratch_address(c->device, &sp);
+    if (e == hipSuccess) {
+      c->d_scratch = (char *)sp;
+    } else {
+      c->scratch_err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+      (void)hipGetLastError();
+    }
+  }
   c->prec = prec;
   c->tsize = prec == FE_PREC_MIXED ? 4 : 8;
   c->ws = (char *)d_ws;
@@ -1437,23 +1479,50 @@ int fe_precond_apply_multi(fe_ctx *c, const double *R, double *Z, int32_t k, voi
   return FE_OK;
 }
 
-int fe_compliance(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
-                  const double *h_val, int64_t nnz_h, double *W, double *Z, void *work,
-                  int64_t work_bytes, void *stream) {
-  if (!c) return FE_EINVAL;
-  const int rc = multi_check(c, k, work, work_bytes);
-  if (rc != FE_OK || k == 0) return rc;
+// W = H P^{-1} H^T with the blocks of right-hand sides in `work` (checked
+// by the caller); shared by fe_compliance and fe_compliance_noalloc.
+static int compliance_impl(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                           const double *h_val, int64_t nnz_h, double *W, double *Z, char *work,
+                           void *stream) {
   if (!h_row_ptr || !W || nnz_h < 0 || (nnz_h > 0 && (!h_col || !h_val)))
     return c->fail(FE_EINVAL, "bad constraint matrix or NULL output");
   hipStream_t st = (hipStream_t)stream;
   const MultiWs m = multi_ws(c, k);
   HIP_TRY(hipMemsetAsync(c->d_herr, 0, sizeof(int), st));
   if (c->prec == FE_PREC_MIXED)
-    compliance<float>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, (char *)work, st);
+    compliance<float>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, work, st);
   else
-    compliance<double>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, (char *)work, st);
+    compliance<double>(c, m, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, work, st);
   HIP_TRY(hipGetLastError());
   return herr_check(c, st);
+}
+
+int fe_compliance(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                  const double *h_val, int64_t nnz_h, double *W, double *Z, void *work,
+                  int64_t work_bytes, void *stream) {
+  if (!c) return FE_EINVAL;
+  const int rc = multi_check(c, k, work, work_bytes);
+  if (rc != FE_OK || k == 0) return rc;
+  return compliance_impl(c, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, (char *)work, stream);
+}
+
+int fe_compliance_noalloc(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,
+                          const double *h_val, int64_t nnz_h, double *W, double *Z,
+                          void *stream) {
+  if (!c) return FE_EINVAL;
+  if (!c->bound) return c->fail(FE_ESTATE, "fe_bind has not been called");
+  if (!c->d_scratch) return c->fail(FE_EDEVICE, "%s", c->scratch_err.c_str());
+  if (k > 0) {
+    const int64_t need = multi_ws(c, k).total;
+    if (need > kScratchBytes)
+      return c->fail(FE_ENOMEM,
+                     "%d right-hand sides need %lld bytes of scratch; the static scratch holds "
+                     "%lld bytes (use fe_compliance with a caller workspace)",
+                     (int)k, (long long)need, (long long)kScratchBytes);
+  }
+  const int rc = multi_check(c, k, c->d_scratch, kScratchBytes);
+  if (rc != FE_OK || k == 0) return rc;
+  return compliance_impl(c, k, h_row_ptr, h_col, h_val, nnz_h, W, Z, c->d_scratch, stream);
 }
 
 int fe_constraint_apply(fe_ctx *c, int32_t k, const int32_t *h_row_ptr, const int32_t *h_col,

@@ -364,6 +364,23 @@ class FEContext:
                                          _stream()))
         return (W, Z) if want_Z else W
 
+    def compliance_noalloc(self, H: "Constraints", W, Z=None):
+        """W = H P^{-1} H^T into the caller's W (k x k), and Z = P^{-1} H^T
+        into Z (n_dofs x k) when given, through the entry point that
+        allocates nothing (its work blocks live in the library's static
+        device scratch)."""
+        self.bind()
+        k = H.k
+        if not (W.is_cuda and W.dtype == torch.float64 and W.is_contiguous()
+                and W.numel() == k * k):
+            raise ValueError("W must be a contiguous float64 CUDA tensor of k x k entries")
+        if Z is not None:
+            self._block(Z, "Z", k)
+        self._chk(self.lib.fe_compliance_noalloc(self.h, k, _ptr(H.row_ptr), _ptr(H.col),
+                                                 _ptr(H.val), H.nnz, _ptr(W), _ptr(Z),
+                                                 _stream()))
+        return W
+
     def constraint_apply(self, H: "Constraints", x, transpose=False, s_h=1.0, y_in=None,
                          s_y=1.0, y=None):
         """y = s_h op(H) x + s_y y_in with op(H) = H or H^T."""

@@ -3,17 +3,33 @@
 20 implicit steps, checkpoints every 5 steps.  Loss L = ||q_T - q_target||^2
 with q_target from a second E field.
 
-dL/dE from the adjoint rollout (autograd Function over fe_step_adjoint) in
-both precision modes (FP64 with solves to rel-res 1e-12; mixed, FP32
-element/SpMV values/triangular solves with FP64 dots and state, solves to
-rel-res 1e-8 as the large mixed workload runs them) is checked against
+dL/dE from the adjoint rollout (autograd Function over fe_step_adjoint).
+
+FP64 (solves to rel-res 1e-12) is checked against
 * central finite differences of the FP64 GPU forward rollout on 20 random
   elements (dE = 1e-4 E_e), to 1e-4 relative (the denominator floored at
   1% of the largest of the 20 differences, for components near zero whose
   difference quotient is dominated by rounding);
 * the oracle's adjoint recursion (banded Cholesky solves), element by
-  element on all 4000 elements (1e-6 of the largest component in FP64,
-  1e-4 in mixed precision).
+  element on all 4000 elements, to 1e-6 of the largest component.
+
+Mixed precision (FP32 element values, A and triangular solves; FP64 state,
+dots and adjoint element pass; solves to rel-res 1e-8 as the large mixed
+workload runs them) computes the gradient of a slightly different forward
+model: A is stored in FP32, which moves each step's acceleration by a few
+1e-7 relative, and after 20 steps q_T differs from the FP64 rollout by
+about 5e-6 of the displacement.  This loss compares q_T with a target that
+is only 0.4% of the displacement away, so that difference is amplified
+about 300 times in dL/dq_T.  The mixed adjoint is therefore checked
+* against the FP64 adjoint driven by the same output sensitivity
+  2 (q_T - q_target) taken from the mixed rollout, to 1e-4 of the largest
+  component: everything but the forward model's rounding is the same;
+* against FP64 finite differences of a loss without that cancellation,
+  L2 = ||q_T - X||^2, to 1e-4 relative as above;
+* against FP64 finite differences and the oracle adjoint of the C4 loss,
+  to 1e-4 plus 10 rho of the largest component, rho = ||q_T(mixed) -
+  q_T(reference)|| / ||q_T(reference) - q_target|| measured in the test
+  (the forward-model difference carried into dL/dq_T).
 """
 import time
 
@@ -76,6 +92,25 @@ def fd_ref(diff):
 
 
 @pytest.fixture(scope="module")
+def fd_ref_disp(diff):
+    """FP64 central differences of L2 = ||q_T - X||^2 on the 20 elements."""
+    w, sim, opts, forward, q_target = diff
+    E = w.E.copy()
+    X = _t(w.q0())
+    fds = []
+    for e in w.extra["fd_elements"]:
+        d = 1e-4 * E[e]
+        Ep, Em = E.copy(), E.copy()
+        Ep[e] += d
+        Em[e] -= d
+        lp = float(((forward(Ep) - X) ** 2).sum())
+        lm = float(((forward(Em) - X) ** 2).sum())
+        fds.append((lp - lm) / (2 * d))
+    print(f"[diff] finite differences of ||q_T - X||^2 on {len(fds)} elements", flush=True)
+    return np.array(fds)
+
+
+@pytest.fixture(scope="module")
 def mixed_sim(diff):
     w = diff[0]
     sim = Simulation(w, prec=FE_PREC_MIXED, factor_on_gpu=True)
@@ -91,23 +126,58 @@ def _gradient(w, sim, opts, q_target):
     return Et.grad.cpu().numpy(), qT.detach().cpu().numpy(), float(loss.detach())
 
 
-@pytest.mark.parametrize("prec", [FE_PREC_FP64, FE_PREC_MIXED])
-def test_adjoint_vs_finite_differences(diff, fd_ref, mixed_sim, prec):
+def _vjp(w, sim, opts, g_qT):
+    """dE of the rollout on `sim` for a given output sensitivity dL/dq_T."""
+    Et = _t(w.E).requires_grad_(True)
+    qT, _ = rollout(Et, _t(w.q0()), _t(w.v0()), sim.ctx, sim.params, NSTEPS, CKPT, opts)
+    (g,) = torch.autograd.grad(qT, Et, grad_outputs=g_qT)
+    return g.cpu().numpy(), qT.detach()
+
+
+def _fd_err(ga, fds):
+    floor = 1e-2 * np.abs(fds).max()
+    return float((np.abs(ga - fds) / np.maximum(np.abs(fds), floor)).max())
+
+
+def test_adjoint_vs_finite_differences_fp64(diff, fd_ref):
     w, sim, opts, forward, q_target = diff
-    if prec == FE_PREC_MIXED:
-        sim, opts = mixed_sim
-    print(f"[diff] adjoint vs FD, prec={prec}", flush=True)
+    print("[diff] FP64 adjoint vs FD", flush=True)
     g, _, loss = _gradient(w, sim, opts, q_target)
     print(f"[diff] adjoint gradient, loss {loss:.6e}", flush=True)
-    fds = fd_ref
     ga = g[w.extra["fd_elements"]]
-    for e, a, f in zip(w.extra["fd_elements"], ga, fds):
+    for e, a, f in zip(w.extra["fd_elements"], ga, fd_ref):
         print(f"  element {e}: adjoint {a:.6e} fd {f:.6e}")
-    floor = 1e-2 * np.abs(fds).max()
-    errs = np.abs(ga - fds) / np.maximum(np.abs(fds), floor)
-    print(f"  max rel err {errs.max():.2e} (plain relative "
-          f"{np.max(np.abs(ga - fds) / np.abs(fds)):.2e})")
-    assert errs.max() <= 1e-4
+    err = _fd_err(ga, fd_ref)
+    print(f"  max rel err {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_mixed_adjoint(diff, fd_ref, fd_ref_disp, mixed_sim):
+    w, sim64, opts64, forward, q_target = diff
+    sim, opts = mixed_sim
+    fe = w.extra["fd_elements"]
+    print("[diff] mixed adjoint", flush=True)
+    g, qT, loss = _gradient(w, sim, opts, q_target)
+    qT = _t(qT)
+    # the same output sensitivity through the FP64 adjoint
+    g64, qT64 = _vjp(w, sim64, opts64, 2 * (qT - q_target))
+    e_cons = float(np.abs(g - g64).max() / np.abs(g64).max())
+    rho = float((qT - qT64).norm() / (qT64 - q_target).norm())
+    e_fwd = float((qT - qT64).norm() / (qT64 - _t(w.q0())).norm())
+    print(f"  forward: |q_T mixed - q_T fp64| / |u| {e_fwd:.2e}, rho {rho:.2e}")
+    print(f"  vs FP64 adjoint with the same dL/dq_T: {e_cons:.2e}")
+    assert e_fwd <= 1e-5
+    assert e_cons <= 1e-4
+    # C4 loss vs FP64 finite differences: the forward-model difference
+    e_fd = float(np.abs(g[fe] - fd_ref).max() / np.abs(fd_ref).max())
+    print(f"  C4 loss vs FD: {e_fd:.2e} of the largest (bound 1e-4 + 10 rho = "
+          f"{1e-4 + 10 * rho:.2e}); floored relative {_fd_err(g[fe], fd_ref):.2e}")
+    assert e_fd <= 1e-4 + 10 * rho
+    # a loss without the cancellation
+    gd, _ = _vjp(w, sim, opts, 2 * (qT - _t(w.q0())))
+    e_disp = _fd_err(gd[fe], fd_ref_disp)
+    print(f"  ||q_T - X||^2 vs FD: max rel err {e_disp:.2e}")
+    assert e_disp <= 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -140,4 +210,7 @@ def test_adjoint_vs_oracle(diff, oracle_ref, mixed_sim, prec):
     if prec == FE_PREC_FP64:
         assert e_fwd <= 1e-9 and e <= 1e-6
     else:
-        assert e_fwd <= 1e-5 and e <= 1e-4
+        # the mixed forward model's difference, carried into dL/dq_T
+        rho = float(np.linalg.norm(qT - qT_o) / np.linalg.norm(qT_o - qt))
+        print(f"  rho {rho:.2e}, bound 1e-4 + 10 rho = {1e-4 + 10 * rho:.2e}")
+        assert e_fwd <= 1e-5 and e <= 1e-4 + 10 * rho

@@ -10,11 +10,14 @@ on the GPU: which matrix a factor is taken from, and the asynchronous swap.
 * Asynchronous mode with the GPU factorisation (tet beam, refresh 3, 12
   steps): factors are swapped in while the rollout runs; every step meets the
   recomputed-residual test and the trajectory matches the oracle's
-  direct-solve rollout.
+  direct-solve rollout (1e-7 in FP64, 1e-4 in mixed precision, whose FP32
+  element arithmetic and A values move the trajectory itself).
 * Asynchronous mode with the host factor thread on one core (differentiation
-  beam, refresh 1, 20 steps): a refresh that falls due while the previous
-  factorisation runs is skipped, so fewer factors are used than refreshes
-  fall due; residuals and trajectory as above.
+  beam, refresh 1, until two factors have been used): a refresh that falls
+  due while the previous factorisation runs is skipped, so the second factor
+  is that of the step at which the first job had finished; every step meets
+  the recomputed-residual test and the trajectory matches a rollout with a
+  fresh factor every step.
 """
 import numpy as np
 import pytest
@@ -87,19 +90,47 @@ def test_async_swap_gpu_factor(prec):
     print(f"[schedule] async GPU factor prec={prec}", flush=True)
     sim = Simulation(w, prec=prec, factor_on_gpu=True)
     opts = sim.opts(rel_tol=1e-10, max_it=3000, refresh=3, lag=0, mode=FE_FACTOR_ASYNC)
-    used = _check_rollout(w, sim, opts, 12, 1e-7)
+    # mixed precision: the FP32 element arithmetic and A values move the
+    # trajectory itself (the bound of the other mixed trajectory tests)
+    used = _check_rollout(w, sim, opts, 12, 1e-7 if prec == FE_PREC_FP64 else 1e-4)
     assert len(set(used)) >= 3, "expected at least three factors swapped in"
     sim.ctx.close()
 
 
 def test_async_skips_refresh_while_busy():
+    # Refresh every step, one host factor thread: a factorisation of the
+    # 14,883-DOF beam takes many steps, so the refreshes that fall due while
+    # it runs are skipped (not queued): the next factor used is that of the
+    # step at which the previous job had finished, not of the next step.
+    # Runs until two factors have been used.  Reference: the same steps with
+    # a fresh GPU factor every step (deterministic schedule); both solve every
+    # step to the same recomputed-residual test.
     w = synth.make("hex_diff")
     print("[schedule] async host factor (one thread), refresh 1", flush=True)
     sim = Simulation(w, prec=FE_PREC_FP64, factor_on_gpu=False, n_threads=1)
-    opts = sim.opts(rel_tol=1e-10, max_it=3000, refresh=1, lag=0, mode=FE_FACTOR_ASYNC)
-    used = _check_rollout(w, sim, opts, 20, 1e-7)
-    n_fact = len(set(used))
-    print(f"  {n_fact} factors used for 20 refreshes due")
-    assert n_fact >= 2, "expected a swap"
-    assert n_fact < 19, "expected refreshes skipped while the factor thread was busy"
+    opts = sim.opts(rel_tol=1e-10, max_it=5000, refresh=1, lag=0, mode=FE_FACTOR_ASYNC)
+    tags = []
+    while len({t for t in tags if t >= 0}) < 2 and len(tags) < 1500:
+        st = sim.step(opts)
+        assert st.solve.status == 0 and st.solve.rel_res <= opts.rel_tol
+        tags.append(int(st.solve.factor_tag))
+    torch.cuda.synchronize()
+    used = sorted({t for t in tags if t >= 0})
+    first_use = [tags.index(t) for t in used]
+    print(f"  {len(tags)} steps, factors {used} first used at steps {first_use}")
+    assert len(used) == 2, "expected a second factor within 1500 steps"
+    assert used[0] == 0 and first_use[0] >= 2, "the first factor should take several steps"
+    # the second job started at the first step after the first had finished
+    # (every refresh due in between was skipped)
+    assert used[1] >= first_use[0] - 1 and used[1] - used[0] >= 2
+    ref = Simulation(w, prec=FE_PREC_FP64, factor_on_gpu=True)
+    ropts = ref.opts(rel_tol=1e-10, max_it=500, refresh=1, lag=0, mode=FE_FACTOR_DETERMINISTIC)
+    for _ in range(len(tags)):
+        ref.step(ropts)
+    torch.cuda.synchronize()
+    u = (ref.q - ref.q.new_tensor(w.q0())).norm()
+    e = float((sim.q - ref.q).norm() / u)
+    print(f"  displacement vs fresh-factor rollout {e:.2e}")
+    assert e <= 1e-6
     sim.ctx.close()
+    ref.ctx.close()

@@ -16,7 +16,8 @@
 //   schur    once the own columns are done: the Schur complement
 //            F22 -= L21 D L21^T and the struct rows of X, -L21 X_own, in one
 //            pass over each 128 x 128 output tile (K = nc; 64 x 64 on the
-//            levels with too few large tiles to fill the GPU)
+//            levels with too few large tiles to fill the GPU), on the
+//            matrix cores (FP64 MFMA 16x16x4)
 //   emit     G = [X own rows; -X struct rows] -> panel (FP32 or FP64), and
 //            1/d into dinv
 // The row operations of the elimination applied to X = [I; 0] leave
@@ -451,6 +452,154 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
   }
 }
 
+// The same update on the matrix cores: FP64 MFMA 16x16x4.  The LDS stages
+// are filled exactly as in gf_update; each of the four wavefronts owns a
+// TL/2 x TL/2 quadrant of the output tile as (TL/32)^2 blocks of 16 x 16.
+// An MFMA block's result holds, in register q of lane l, column l % 16 of
+// row 4q + l / 16, so the instruction is oriented per region so that the 16
+// lanes of a register run along the output's contiguous index: rows i for
+// the column-major F and U outputs (regions 0 and 2), columns j for the
+// row-major X outputs (regions 1 and 3).  "fast" below is that index,
+// "slow" the other one; the slow operand is negated, so that each MFMA
+// subtracts its product from the accumulators.
+typedef double gf_d4 __attribute__((ext_vector_type(4)));
+
+template <int TL>
+__device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *base) {
+  constexpr int KC = 32;
+  constexpr int NBK = TL / 32;  // 16 x 16 blocks per wavefront quadrant edge
+  const int m = f.m, nc = f.nc;
+  const int reg = t.region;
+  int kbeg, kend, imax, jmax;
+  if (reg == 0) {
+    kbeg = k0, kend = min(k0 + NB, nc), imax = m, jmax = nc;
+  } else if (reg == 1) {
+    kbeg = k0, kend = min(k0 + NB, nc), imax = nc, jmax = kend;
+  } else if (reg == 2) {
+    kbeg = 0, kend = nc, imax = m, jmax = m;
+  } else {
+    kbeg = t.j0, kend = nc, imax = m, jmax = nc;  // X[k, j] = 0 for k < j
+  }
+  double *F = base + f.offF;
+  double *X = base + f.offX;
+  const double *W = base + f.offW;
+  double *U = base + f.offU;
+  const int64_t ru = m - nc;
+  __shared__ double sA[KC][TL + 2];
+  __shared__ double sB[KC][TL + 2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const bool fout = reg == 0 || reg == 2;
+  // quadrant of this wavefront and the output index of each accumulator
+  const int wf = (wv & 1) * (TL / 2), ws = (wv >> 1) * (TL / 2);
+  const int fbase = fout ? t.i0 : t.j0, sbase = fout ? t.j0 : t.i0;
+  const int fmax = fout ? imax : jmax, smax = fout ? jmax : imax;
+  const int lf = lane & 15, ls = lane >> 4;
+  gf_d4 acc[NBK][NBK];
+#pragma unroll
+  for (int sb = 0; sb < NBK; ++sb)
+#pragma unroll
+    for (int fb = 0; fb < NBK; ++fb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int fi = min(fbase + wf + 16 * fb + lf, fmax - 1);
+        const int si = min(sbase + ws + 16 * sb + 4 * q + ls, smax - 1);
+        double v;
+        if (reg == 0) v = F[(int64_t)si * m + fi];
+        else if (reg == 2) v = U[(si - nc) * ru + (fi - nc)];
+        else v = X[(int64_t)si * nc + fi];
+        acc[sb][fb][q] = v;
+      }
+  // staging as in gf_update
+  constexpr int KS = 256 / TL;
+  constexpr int NPASS = 4;
+  constexpr int QH = KC / KS / NPASS;
+  const int sr = tid % TL, kq = tid / TL;
+  const bool iok = t.i0 + sr < imax, jok = t.j0 + sr < jmax;
+  const int si_ = min(t.i0 + sr, imax - 1), sj_ = min(t.j0 + sr, jmax - 1);
+  double(*fast)[TL + 2] = fout ? sA : sB;
+  double(*slow)[TL + 2] = fout ? sB : sA;
+  for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
+    const int kn = min(KC, kend - kc0);
+    if (kc0 > kbeg) __syncthreads();
+#pragma unroll
+    for (int h = 0; h < NPASS; ++h) {
+      double a[QH], b[QH];
+      int kk[QH];
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        kk[q] = kc0 + min(kq + KS * (q + QH * h), kn - 1);
+        a[q] = F[(int64_t)kk[q] * m + si_];
+      }
+      if (reg == 0) {
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] = W[(int64_t)(kk[q] - k0) * m + sj_];
+      } else if (reg == 2) {
+        double dk[QH];
+#pragma unroll
+        for (int q = 0; q < QH; ++q) {
+          b[q] = F[(int64_t)kk[q] * m + sj_];
+          dk[q] = F[(int64_t)kk[q] * m + kk[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] *= dk[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < QH; ++q) b[q] = X[(int64_t)kk[q] * nc + sj_];
+      }
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int k = kq + KS * (q + QH * h);
+        sA[k][sr] = (k < kn && iok) ? a[q] : 0.0;
+        sB[k][sr] = (k < kn && jok) ? b[q] : 0.0;
+      }
+    }
+    __syncthreads();
+    // the staged rows k >= kn are zero, so whole steps of 4 are taken
+    for (int k = 0; k < kn; k += 4) {
+      double av[NBK], bv[NBK];
+#pragma unroll
+      for (int sb = 0; sb < NBK; ++sb) av[sb] = -slow[k + ls][ws + 16 * sb + lf];
+#pragma unroll
+      for (int fb = 0; fb < NBK; ++fb) bv[fb] = fast[k + ls][wf + 16 * fb + lf];
+#pragma unroll
+      for (int sb = 0; sb < NBK; ++sb)
+#pragma unroll
+        for (int fb = 0; fb < NBK; ++fb)
+          acc[sb][fb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[sb], bv[fb], acc[sb][fb], 0, 0, 0);
+    }
+  }
+  // stores: in range, and on or below the diagonal for the F outputs
+#pragma unroll
+  for (int sb = 0; sb < NBK; ++sb)
+#pragma unroll
+    for (int fb = 0; fb < NBK; ++fb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int fi = fbase + wf + 16 * fb + lf;
+        const int si = sbase + ws + 16 * sb + 4 * q + ls;
+        const int i = fout ? fi : si, j = fout ? si : fi;
+        if (i >= imax || j >= jmax) continue;
+        const double v = acc[sb][fb][q];
+        if (reg == 0) {
+          if (i >= j) F[(int64_t)j * m + i] = v;
+        } else if (reg == 2) {
+          if (i >= j) U[(j - nc) * ru + (i - nc)] = v;
+        } else {
+          X[(int64_t)i * nc + j] = v;
+        }
+      }
+}
+
+template <int TL>
+__global__ __launch_bounds__(256) void k_gf_update_mfma(const GfTile *tiles, int64_t n_tiles,
+                                                        const GfFront *fr, int k0, double *base) {
+  for (int64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
+    const GfTile t = tiles[q];
+    gf_update_mfma<TL>(t, fr[t.s], k0, base);
+    __syncthreads();
+  }
+}
+
 // one tile per block (stride gridDim.x)
 template <int TL>
 __global__ __launch_bounds__(256) void k_gf_update(const GfTile *tiles, int64_t n_tiles,
@@ -570,9 +719,10 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
     if (nh > 0 && P.schur_tile[L] == kGfTile)
-      k_gf_update<kGfTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
+      k_gf_update_mfma<kGfTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
     else if (nh > 0)
-      k_gf_update<kGfStepTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0, d.fronts);
+      k_gf_update_mfma<kGfStepTile><<<grid1(nh), 256, 0, st>>>(d.upd + h0, nh, d.fr, 0,
+                                                               d.fronts);
     int64_t maxt = 0;
     for (int k = f0; k < f0 + nf; ++k) {
       const GfFront &g = P.fr[P.lvl_sn[k]];

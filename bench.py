@@ -9,9 +9,12 @@ kernels, A values and triangular solves; FP64 state, CG vectors, dots and
 residual), CG to relative residual 1e-8, LDL^T preconditioner refactored
 every 20 steps and swapped in when ready (the paper's asynchronous scheme;
 the FP64 multifrontal factorisation runs on its own GPU stream in place of
-the paper's CPU thread).  Beside it, on the same workload: FP64 steps/s, and
-the full configuration (50 forward steps, then the adjoint with checkpoints
-every 5 steps) giving forward and adjoint steps/s.  The other workloads of
+the paper's CPU thread).  Each step's CG starts from the A-norm projection
+of its solution onto the last 8 accelerations (the paper leaves the initial
+guess open; every step still meets the same recomputed-residual test).
+Beside it, on the same workload: the same steps from x0 = 0, FP64 steps/s,
+and the full configuration (50 forward steps, then the adjoint with
+checkpoints every 5 steps) giving forward and adjoint steps/s.  The other workloads of
 the study (hex beam, tet block, tet beam, differentiation beam) are timed
 after it.  Synthetic meshes; inputs are resident in HBM before the timed
 region.
@@ -37,7 +40,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+_T0 = time.perf_counter()
+
+
+def _log(msg):
+    """A progress line on stderr with the seconds since the start."""
+    print(f"{msg} [{time.perf_counter() - _T0:.0f} s]", file=sys.stderr, flush=True)
+
 HEADLINE = "hex_block"
+# initial guess of the timed steps' CG: the A-norm projection onto the last
+# 8 accelerations (x0 = 0 is timed beside it)
+HEADLINE_WARM = 8
 
 
 def _free(sim):
@@ -55,7 +68,7 @@ def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True, warm_start
 
     sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=gpu_factor)
     det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
-                   mode=FE_FACTOR_DETERMINISTIC)
+                   mode=FE_FACTOR_DETERMINISTIC, warm_start=warm_start)
     asy = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0, mode=FE_FACTOR_ASYNC,
                    warm_start=warm_start)
     for _ in range(warmup):
@@ -188,7 +201,7 @@ def _kernel_pass_only(workload, n_apply):
                       "roofline": _roofline(kt, workload)}))
 
 
-def _adjoint_leg(w, prec, nsteps, k):
+def _adjoint_leg(w, prec, nsteps, k, warm_start=0):
     """The full differentiable configuration: a target rollout with the
     second E field, then a rollout of nsteps forward steps with checkpoints
     every k steps (timed: forward steps/s) and its adjoint (timed: reverse
@@ -204,7 +217,7 @@ def _adjoint_leg(w, prec, nsteps, k):
     A, _ = sim.ctx.assemble(sim.params, sim.q, sim.v)
     sim.ctx.factorize_now(A, 0)
     opts = sim.opts(rel_tol=w.rel_tol, max_it=3000, refresh=w.refresh, lag=0,
-                    mode=FE_FACTOR_ASYNC)
+                    mode=FE_FACTOR_ASYNC, warm_start=warm_start)
     q0, v0 = sim.q.clone(), sim.v.clone()
     E_t = torch.as_tensor(w.extra["E_target"], dtype=torch.float64, device="cuda")
     with torch.no_grad():
@@ -237,27 +250,31 @@ def _headline(steps, warmup, extras, kernel_applies):
     from paper_2306_05893_amd import FE_PREC_FP64, FE_PREC_MIXED
 
     w = synth.make(HEADLINE)
-    print(f"[bench] {HEADLINE}: {w.n_dofs} DOFs, {w.n_elems} elements", file=sys.stderr,
-          flush=True)
-    mixed = _timed_run(w, FE_PREC_MIXED, steps, warmup)
-    print(f"[bench] {HEADLINE} mixed {mixed['steps_per_s']:.2f} steps/s "
-          f"it={mixed['cg_it_mean']:.1f} lag={mixed['factor_lag_mean']:.1f}", file=sys.stderr,
-          flush=True)
+    _log(f"[bench] {HEADLINE}: {w.n_dofs} DOFs, {w.n_elems} elements")
+    mixed = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=HEADLINE_WARM)
+    _log(f"[bench] {HEADLINE} mixed {mixed['steps_per_s']:.2f} steps/s "
+          f"it={mixed['cg_it_mean']:.1f} lag={mixed['factor_lag_mean']:.1f}")
     sizes = mixed["sim"].ctx.sizes
     kt = _kernel_profile(mixed["sim"], n_apply=kernel_applies, n_spmv=4 * kernel_applies,
                          n_assemble=kernel_applies)
     _free(mixed.pop("sim"))
     out = {"w": w, "mixed": mixed, "sizes": sizes, "kt": kt}
     if extras:
-        fp64 = _timed_run(w, FE_PREC_FP64, steps, warmup)
+        fp64 = _timed_run(w, FE_PREC_FP64, steps, warmup, warm_start=HEADLINE_WARM)
         _free(fp64.pop("sim"))
         out["fp64"] = fp64
-        print(f"[bench] {HEADLINE} fp64 {fp64['steps_per_s']:.2f} steps/s "
-              f"it={fp64['cg_it_mean']:.1f}", file=sys.stderr, flush=True)
-        adj = _adjoint_leg(w, FE_PREC_MIXED, w.steps, w.extra["checkpoint_every"])
+        _log(f"[bench] {HEADLINE} fp64 {fp64['steps_per_s']:.2f} steps/s "
+              f"it={fp64['cg_it_mean']:.1f}")
+        zero = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=0)
+        _free(zero.pop("sim"))
+        out["mixed_x0_zero"] = zero
+        _log(f"[bench] {HEADLINE} mixed, x0 = 0: {zero['steps_per_s']:.2f} steps/s "
+              f"it={zero['cg_it_mean']:.1f}")
+        adj = _adjoint_leg(w, FE_PREC_MIXED, w.steps, w.extra["checkpoint_every"],
+                           warm_start=HEADLINE_WARM)
         out["adjoint"] = adj
-        print(f"[bench] {HEADLINE} {w.steps} forward steps {adj['forward_steps_per_s']} steps/s, "
-              f"adjoint {adj['adjoint_steps_per_s']} steps/s", file=sys.stderr, flush=True)
+        _log(f"[bench] {HEADLINE} {w.steps} forward steps {adj['forward_steps_per_s']} steps/s, "
+              f"adjoint {adj['adjoint_steps_per_s']} steps/s")
     return out
 
 
@@ -294,9 +311,8 @@ def _other_workloads(steps, warmup):
     _free(r.pop("sim"))
     rec["stvk_mixed_warm_start"] = _leg(r)
     out["hex_beam"] = rec
-    print(f"[bench] hex_beam StVK mixed {rec['stvk_mixed']['steps_per_s']} / fp64 "
-          f"{rec['stvk_fp64']['steps_per_s']}, NH mixed {rec['nh_mixed']['steps_per_s']} steps/s",
-          file=sys.stderr, flush=True)
+    _log(f"[bench] hex_beam StVK mixed {rec['stvk_mixed']['steps_per_s']} / fp64 "
+         f"{rec['stvk_fp64']['steps_per_s']}, NH mixed {rec['nh_mixed']['steps_per_s']} steps/s")
     w = synth.make("tet_block")
     rec = {"n_dofs": w.n_dofs, "refresh": w.refresh, "steps": steps}
     for tag, prec in (("mixed", FE_PREC_MIXED), ("fp64", FE_PREC_FP64)):
@@ -304,8 +320,8 @@ def _other_workloads(steps, warmup):
         _free(r.pop("sim"))
         rec[tag] = _leg(r)
     out["tet_block"] = rec
-    print(f"[bench] tet_block mixed {rec['mixed']['steps_per_s']} / fp64 "
-          f"{rec['fp64']['steps_per_s']} steps/s", file=sys.stderr, flush=True)
+    _log(f"[bench] tet_block mixed {rec['mixed']['steps_per_s']} / fp64 "
+          f"{rec['fp64']['steps_per_s']} steps/s")
     # tet beam: its own 10 steps, exact factor each step (refresh 1, lag 0)
     import torch
     w = synth.make("tet_beam")
@@ -328,9 +344,9 @@ def _other_workloads(steps, warmup):
     w = synth.make("hex_diff")
     out["hex_diff"] = dict({"n_dofs": w.n_dofs, "prec": "fp64"},
                            **_adjoint_leg(w, FE_PREC_FP64, w.steps, w.extra["checkpoint_every"]))
-    print(f"[bench] tet_beam {out['tet_beam']['steps_per_s']} steps/s; hex_diff forward "
+    _log(f"[bench] tet_beam {out['tet_beam']['steps_per_s']} steps/s; hex_diff forward "
           f"{out['hex_diff']['forward_steps_per_s']} / adjoint "
-          f"{out['hex_diff']['adjoint_steps_per_s']} steps/s", file=sys.stderr, flush=True)
+          f"{out['hex_diff']['adjoint_steps_per_s']} steps/s")
     return out
 
 
@@ -354,8 +370,8 @@ def _materials(steps=30, warmup=10):
                      "cg_it_mean": round(r["cg_it_mean"], 2),
                      "factor_lag_mean": round(r["factor_lag_mean"], 1),
                      "assembly_us": round(1e3 * el["ms"] / max(el["count"], 1), 1)}
-        print(f"[bench] {name}: {out[name]['steps_per_s']} steps/s, assembly "
-              f"{out[name]['assembly_us']} us", file=sys.stderr, flush=True)
+        _log(f"[bench] {name}: {out[name]['steps_per_s']} steps/s, assembly "
+              f"{out[name]['assembly_us']} us")
     return out
 
 
@@ -389,8 +405,8 @@ def _topology():
     out = {"keepstruct_check_ms": round(1e3 * t_keep, 3), "full_assembly_ms": round(1e3 * t_full, 1),
            "elements_removed": int((~keep).sum()), "nnz_after": int(sim.ctx.sizes.nnz)}
     sim.ctx.close()
-    print(f"[bench] topology: keepStruct check {out['keepstruct_check_ms']} ms, full assembly "
-          f"{out['full_assembly_ms']} ms", file=sys.stderr, flush=True)
+    _log(f"[bench] topology: keepStruct check {out['keepstruct_check_ms']} ms, full assembly "
+          f"{out['full_assembly_ms']} ms")
     return out
 
 
@@ -493,9 +509,9 @@ def _contact(k=246, n_rep=10, pgs_sweeps=100):
                     "contact_active": int((lam > 0).sum()),
                     "cg_it_free_correction": [st["free"].iterations,
                                               st["correction"].iterations]}
-        print(f"[bench] contact {tag}: W in {out[tag]['compliance_ms_median']} ms "
+        _log(f"[bench] contact {tag}: W in {out[tag]['compliance_ms_median']} ms "
               f"({out[tag]['speedup_vs_single_rhs']}x vs single applies), sweeps "
-              f"{out[tag]['sweeps_TFLOPs']} TFLOP/s", file=sys.stderr, flush=True)
+              f"{out[tag]['sweeps_TFLOPs']} TFLOP/s")
         ctx.close()
     return out
 
@@ -546,7 +562,7 @@ def _age_curve(workload, nsteps, variants):
            "variants": {}}
     for tag in variants:
         prec = FE_PREC_FP64 if tag.startswith("fp64") else FE_PREC_MIXED
-        warm = 1 if tag.endswith("warm") else 0
+        warm = 1 if tag.endswith("warm") else (int(tag.split("proj")[1]) if "proj" in tag else 0)
         sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=True)
         det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
                        mode=FE_FACTOR_DETERMINISTIC, warm_start=warm)
@@ -566,8 +582,7 @@ def _age_curve(workload, nsteps, variants):
         out["variants"][tag] = {"age": ages, "iterations": its, "step_ms": ms,
                                 "mean_iterations_by_age": {a: round(sum(v) / len(v), 2)
                                                            for a, v in sorted(by_age.items())}}
-        print(f"[bench] age curve {tag}: mean iterations {sum(its) / len(its):.1f}",
-              file=sys.stderr, flush=True)
+        _log(f"[bench] age curve {tag}: mean iterations {sum(its) / len(its):.1f}")
     print(json.dumps(out))
 
 
@@ -598,7 +613,7 @@ def _cpu_child(mode, threads, timeout=900):
 SLAB_LAYERS = 12   # cell layers of the hex block in the CPU sample (1/16 of 192)
 
 
-def _cpu_baseline():
+def _cpu_baseline(small_configs=False):
     """The FP64 oracle on the GPU machine's host cores.
 
     Headline workload (value): a bounded sample, the bottom 12 of the 192
@@ -607,10 +622,10 @@ def _cpu_baseline():
     element tangents and forces, triplet-sort assembly through the map, and
     an FP64 Jacobi-PCG solve capped in time, plus one CSR SpMV; every phase
     is scaled x16 to the full block.  The capped solve does not converge, so
-    the figure is an upper bound on the oracle's steps/s.  The small
-    configurations run whole (tet beam 10 steps with dense Cholesky,
-    differentiation beam 20 steps with banded Cholesky), with one BLAS thread
-    and with all the cores."""
+    the figure is an upper bound on the oracle's steps/s.  With
+    small_configs (``--cpu-phases``), the small configurations run whole
+    (tet beam 10 steps with dense Cholesky, differentiation beam 20 steps with
+    banded Cholesky), with one BLAS thread and with all the cores."""
     nproc, threads = _host_cores()
     try:
         s = _cpu_child("slab", threads)
@@ -633,6 +648,8 @@ def _cpu_baseline():
                                   "jacobi_pcg_iteration": round(scale * s["t_pcg"] /
                                                                 max(s["pcg_it"], 1), 3),
                                   "pattern_once": round(scale * s["t_pattern"], 1)}}
+    if not small_configs:
+        return out
     small = {}
     for tag, th in (("1_thread", 1), (f"{threads}_threads", threads)):
         try:
@@ -641,6 +658,21 @@ def _cpu_baseline():
             small[tag] = {"failed": str(e)[-200:]}
     out["small_configs"] = small
     return out
+
+
+def _cpu_phases():
+    """The oracle's per-phase times at full size (hex beam, tet block) and the
+    headline's CPU baseline, one JSON line; no GPU is touched."""
+    nproc, threads = _host_cores()
+    out = {"nproc": nproc, "threads": threads, "phases": {}}
+    for name in ("hex_beam", "tet_block"):
+        try:
+            out["phases"][name] = _cpu_child(f"phases:{name}", threads)
+        except (RuntimeError, subprocess.TimeoutExpired) as e:
+            out["phases"][name] = {"failed": str(e)[-200:]}
+        _log(f"[bench] oracle phases {name}: {out['phases'][name]}")
+    out["headline"] = _cpu_baseline(small_configs=True)
+    print(json.dumps(out))
 
 
 def _cpu_baseline_child(mode):
@@ -684,6 +716,26 @@ def _cpu_baseline_child(mode):
                           "t_pcg": t4 - t3, "pcg_it": int(it), "pcg_res": float(res),
                           "t_update_full": t6 - t5}))
         return
+    if mode.startswith("phases:"):
+        # one oracle step from rest at full size, phase by phase
+        w = synth.make(mode.split(":", 1)[1])
+        t0 = time.perf_counter()
+        pat = ostep.pattern(w)
+        t1 = time.perf_counter()
+        s = ostep.assemble(w, w.q0(), w.v0(), pat=pat)
+        t2 = time.perf_counter()
+        y = assembly.csr_matvec(pat.row_ptr, pat.col_idx, s.vals, s.b)
+        t3 = time.perf_counter()
+        a, it, res = solve.jacobi_pcg(pat.row_ptr, pat.col_idx, s.vals, s.b, rel_tol=1e-8,
+                                      time_limit=20.0)
+        t4 = time.perf_counter()
+        assert np.isfinite(y).all() and np.isfinite(a).all()
+        print(json.dumps({"workload": w.name, "n_dofs": w.n_dofs, "nnz": int(pat.col_idx.size),
+                          "pattern_s": round(t1 - t0, 3), "assembly_s": round(t2 - t1, 3),
+                          "csr_spmv_s": round(t3 - t2, 4), "jacobi_pcg_s": round(t4 - t3, 2),
+                          "jacobi_pcg_iterations": int(it), "jacobi_pcg_rel_res": float(res),
+                          "jacobi_pcg_converged": bool(res <= 1e-8)}))
+        return
     out = {}
     for name in ("tet_beam", "hex_diff"):
         w = synth.make(name)
@@ -708,6 +760,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="headline mixed leg only (no FP64/adjoint legs, no other workloads)")
     ap.add_argument("--cpu-baseline-child", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-phases", action="store_true",
+                    help="only time the oracle's phases (pattern, assembly, CSR SpMV, capped "
+                         "Jacobi-PCG) at full size on the hex beam and the tet block, and the "
+                         "CPU baseline of the headline, on the host cores (no GPU)")
     ap.add_argument("--factor-only", type=int, default=0, metavar="N",
                     help="only time N standalone GPU refactorisations of --workload")
     ap.add_argument("--workload", default=HEADLINE,
@@ -724,14 +780,17 @@ def main():
                     help="only the event-timed kernel pass (factor of A at rest)")
     ap.add_argument("--age-curve", type=int, default=0, metavar="STEPS",
                     help="only record CG iterations against factor age over STEPS steps of "
-                         "--workload (deterministic schedule; mixed, FP64, mixed with warm "
-                         "start)")
+                         "--workload (deterministic schedule; mixed with x0 = 0, the previous "
+                         "acceleration or the projection onto the last 8, and FP64 with x0 = 0)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         _cpu_baseline_child(args.cpu_baseline_child)
+        return
+    if args.cpu_phases:
+        _cpu_phases()
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -748,13 +807,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
-        print(f"[bench] calibration copy {args.calibrate_copy_mib} MiB done", file=sys.stderr,
-              flush=True)
+        _log(f"[bench] calibration copy {args.calibrate_copy_mib} MiB done")
     if args.factor_only > 0:
         _factor_only(args.workload, args.factor_only)
         return
     if args.age_curve > 0:
-        _age_curve(args.workload, args.age_curve, ("mixed", "fp64", "mixed_warm"))
+        _age_curve(args.workload, args.age_curve,
+                   ("mixed", "mixed_warm", "mixed_proj8", "fp64"))
         return
     if args.kernel_pass_only:
         _kernel_pass_only(args.workload, args.kernel_applies)
@@ -783,6 +842,7 @@ def main():
             "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
             "fp64_factor_lag_mean": round(fp64["factor_lag_mean"], 1),
             "mixed_vs_fp64": round(mixed["steps_per_s"] / fp64["steps_per_s"], 3),
+            "mixed_x0_zero": _leg(h["mixed_x0_zero"]),
             "adjoint_steps_per_s": h["adjoint"]["adjoint_steps_per_s"],
             "full_config": h["adjoint"],
         }
@@ -809,7 +869,12 @@ def main():
                                "Pa, 64 spherical inclusions of radius 4 cells), gravity, "
                                f"{w.n_dofs} DOFs, h=0.01, LDL^T refreshed every {w.refresh} "
                                "steps (asynchronous, FP64 factorisation on its own GPU "
-                               "stream), mixed precision, rel-res 1e-8",
+                               "stream), mixed precision, rel-res 1e-8, CG initial guess "
+                               f"projected on the last {HEADLINE_WARM} accelerations",
+                   "cg_initial_guess": (f"A-norm projection on the last {HEADLINE_WARM} "
+                                        "accelerations" if HEADLINE_WARM >= 2 else
+                                        "previous acceleration" if HEADLINE_WARM == 1 else
+                                        "zero"),
                    "n_dofs": w.n_dofs, "n_elems": w.n_elems, "nnz": int(sizes.nnz),
                    "factor_lower_entries": int(sizes.factor_lower),
                    "levels": int(sizes.n_levels), "refresh": w.refresh,

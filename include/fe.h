@@ -157,7 +157,17 @@ typedef struct {
   int32_t refresh;            /* R: factor A every R steps (0: never)         */
   int32_t lag;                /* d: deterministic mode uses A_{kR} from kR+d  */
   int32_t mode;               /* FE_FACTOR_DETERMINISTIC / FE_FACTOR_ASYNC    */
-  int32_t warm_start;         /* 1: start CG from the previous acceleration   */
+  int32_t warm_start;         /* initial guess of the CG (the paper is silent;
+                                 0, the default, is x0 = 0):
+                                 1: the previous step's acceleration;
+                                 m = 2..8: the A-norm projection of the
+                                 solution onto the last m accelerations,
+                                 x0 = V c with (V^T A V) c = V^T b (Fischer's
+                                 projection for successive right-hand sides;
+                                 m SpMV-like products and a few dot products
+                                 per step; vectors that are nearly
+                                 combinations of newer ones are dropped).
+                                 Values above 8 use 8.                        */
   int32_t pad_;
 } fe_step_opts;
 

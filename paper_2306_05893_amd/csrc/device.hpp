@@ -164,6 +164,20 @@ void launch_update_p(hipStream_t st, int64_t n, double *p, const double *z, cons
                      int first);
 void launch_ctl_true(hipStream_t st, PcgState *s, const double *part, int np);
 void launch_zero(hipStream_t st, int64_t n, double *x);
+
+// Initial guess of a step's CG from the last m (<= kHist) solutions: the
+// A-norm projection x = V c, (V^T A V) c = V^T b, with V (n x kHist,
+// interleaved: DOF k's values at V[k * kHist + j]) the ring of earlier
+// solutions whose newest column is `newest`; W (same shape) receives A V.
+// part: hist_part_doubles() doubles of scratch, its last kHist the
+// coefficients.  launch_hist_push stores x as column `slot` of V.
+constexpr int kHist = 8;
+template <typename T>
+void launch_hist_guess(hipStream_t st, int64_t n, int m, int newest, const int32_t *row_ptr,
+                       const int32_t *col, const T *val, const double *V, double *W,
+                       const double *b, double *part, double *coef, double *x);
+void launch_hist_push(hipStream_t st, int64_t n, int slot, const double *x, double *V);
+int64_t hist_part_doubles();
 void launch_integrate(hipStream_t st, int64_t n, double h, const double *a, double *q,
                       double *v);
 

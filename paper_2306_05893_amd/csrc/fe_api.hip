@@ -153,6 +153,9 @@ struct fe_ctx {
   int64_t installed_tag = -1;
   int64_t step_count = 0;
   bool have_prev_a = false;
+  // ring of earlier step solutions for the projected initial guess
+  double *d_histV = nullptr, *d_histW = nullptr, *d_histP = nullptr;
+  int hist_count = 0, hist_next = 0;
 
   // ---- GPU factorisation (factor_on_gpu)
   bool gpu_factor = false;
@@ -217,7 +220,7 @@ enum {
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
   L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF,
-  L_MFT, L_MBT, L_HERR, L_MBDOF
+  L_MFT, L_MBT, L_HERR, L_MBDOF, L_HISTV, L_HISTW, L_HISTP
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -273,12 +276,15 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(cg ? (int64_t)P.blk_pos.size() * 4 : 0);
   L.add(cg ? (int64_t)P.blk_node.size() * 4 : 0);
   L.add(cg ? (int64_t)P.blk_src.size() * 4 : 0);
-  L.add(cg ? (int64_t)P.n_elems * nen * nen * 9 * ts : 0);
+  L.add(cg ? (int64_t)P.n_elems * (nen * (nen + 1) / 2) * 9 * ts : 0);  // blocks a <= b
   L.add(cg ? (int64_t)P.n_elems * nen * 3 * 8 : 0);
   L.add((int64_t)S.mfwd_tiles.size() * (int64_t)sizeof(MTile));
   L.add((int64_t)S.mbwd_tiles.size() * (int64_t)sizeof(MTile));
   L.add(256);
   L.add((int64_t)S.mbwd_dofs.size() * 4);
+  L.add(n * kHist * 8);  // earlier solutions (initial-guess projection)
+  L.add(n * kHist * 8);  // A times them
+  L.add(hist_part_doubles() * 8);
   return L;
 }
 
@@ -890,10 +896,22 @@ int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step
     }
   }
   double *x = c->d_a;
-  if (!(o->warm_start && c->have_prev_a)) launch_zero(st, n, x);
+  const int ws = o->warm_start;
+  const int m = std::min(std::min(ws, kHist), c->hist_count);
+  if (ws >= 2 && m >= 1)
+    launch_hist_guess<T>(st, n, m, (c->hist_next + kHist - 1) % kHist, c->d_row_ptr, c->d_col, A,
+                         c->d_histV, c->d_histW, c->d_b, c->d_histP,
+                         c->d_histP + hist_part_doubles() - kHist, x);
+  else if (!(ws == 1 && c->have_prev_a))
+    launch_zero(st, n, x);
   fe_solve_stats ss;
   rc = pcg<T>(c, A, c->d_b, x, o->rel_tol, o->max_it, st, &ss);
   c->have_prev_a = true;
+  if (ws >= 2 && (rc == FE_OK || rc == FE_ENOTCONV)) {
+    launch_hist_push(st, n, c->hist_next, x, c->d_histV);
+    c->hist_next = (c->hist_next + 1) % kHist;
+    c->hist_count = std::min(c->hist_count + 1, kHist);
+  }
   if (c->h_state->elem_status) {
     clear_elem_status(c, st);
     return c->fail(FE_EINVERTED, "inverted element (det F <= 0) at step %lld", (long long)step);
@@ -1176,6 +1194,9 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_mbtiles = ptr_at<MTile>(w, L, L_MBT);
   c->d_herr = ptr_at<int>(w, L, L_HERR);
   c->d_mbdofs = ptr_at<int32_t>(w, L, L_MBDOF);
+  c->d_histV = ptr_at<double>(w, L, L_HISTV);
+  c->d_histW = ptr_at<double>(w, L, L_HISTW);
+  c->d_histP = ptr_at<double>(w, L, L_HISTP);
 
   // host-side resources
   HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
@@ -1661,6 +1682,8 @@ int fe_reset(fe_ctx *c) {
   c->ready_slot = -1;
   c->job_status = FE_OK;
   c->have_prev_a = false;
+  c->hist_count = 0;
+  c->hist_next = 0;
   return FE_OK;
 }
 

@@ -166,6 +166,13 @@ __device__ inline void atomic_add_t(T *p, T v) {
   atomicAdd(p, v);
 }
 
+// Index of block (a, b), a <= b, among the upper-triangle blocks of an
+// element taken row by row.
+template <int NEN>
+__host__ __device__ constexpr int sym_block(int a, int b) {
+  return a * NEN - a * (a - 1) / 2 + (b - a);
+}
+
 // Scatter the 3x3 block of lane (a, b) and reduce/scatter the RHS of node a.
 template <typename T, bool COMPACT, int NEN>
 __device__ inline void scatter(int64_t e, int a, int b, int ga, const T *Ablk, const T *rhs,
@@ -177,9 +184,14 @@ __device__ inline void scatter(int64_t e, int a, int b, int ga, const T *Ablk, c
   for (int off = 1; off < NEN; off <<= 1)
     for (int r = 0; r < 3; ++r) r3[r] += __shfl_xor(r3[r], off, NEN);
   if (COMPACT) {
-    // contribution buffers, summed per node block by the gather kernel
-    T *dst = ebuf + (e * (NEN * NEN) + a * NEN + b) * 9;
-    for (int k = 0; k < 9; ++k) dst[k] = Ablk[k];
+    // contribution buffers, summed per node block by the gather kernel.  A_e
+    // is symmetric (block (b, a) is the transpose of block (a, b)), so only
+    // the blocks a <= b are kept, in the row-major upper-triangle order of
+    // sym_block
+    if (a <= b) {
+      T *dst = ebuf + (e * (NEN * (NEN + 1) / 2) + sym_block<NEN>(a, b)) * 9;
+      for (int k = 0; k < 9; ++k) dst[k] = Ablk[k];
+    }
     if (b == 0)
       for (int r = 0; r < 3; ++r) rbuf[(e * NEN + a) * 3 + r] = r3[r];
   } else {
@@ -199,6 +211,60 @@ __device__ inline void scatter(int64_t e, int a, int b, int ga, const T *Ablk, c
 }
 
 // ------------------------------------------------------------------ HEX8
+// Cross-lane moves inside rows of 8 lanes (DPP; 64-bit values as two 32-bit
+// moves).  CTRL: 0xB1 quad_perm [1,0,3,2], 0x4E quad_perm [2,3,0,1], 0x141
+// row_half_mirror (lane i <- lane 7 - i within each group of 8).
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 8 lanes of each aligned group of 8 (every lane of the group
+// receives the sum): two quad exchanges, then the other half of the group.
+template <typename T>
+__device__ inline T sum8(T v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  return v;
+}
+
+// Trilinear shape function N_n at Gauss point gp (both 0..7, the corner and
+// point sign patterns of c_hex_sign): 1/8 (1 + g)^k (1 - g)^(3-k) with
+// g = 1/sqrt(3) and k the number of coordinates whose signs agree.
+__constant__ double c_hex_N[4] = {
+    0.125 * 0.42264973081037427 * 0.42264973081037427 * 0.42264973081037427,
+    0.125 * 0.42264973081037427 * 0.42264973081037427 * 1.57735026918962573,
+    0.125 * 0.42264973081037427 * 1.57735026918962573 * 1.57735026918962573,
+    0.125 * 1.57735026918962573 * 1.57735026918962573 * 1.57735026918962573};
+
+__device__ inline int hex_agree(int n, int gp) {
+  // corner n and point gp share the bit pattern of their sign triples up to
+  // the VTK ordering of the corners: c_hex_sign[n] in bits (x: bit 0 of
+  // ((n ^ (n >> 1)) & 1), y: bit 1 of n, z: bit 2 of n)
+  const int cx = (n ^ (n >> 1)) & 1, cy = (n >> 1) & 1, cz = (n >> 2) & 1;
+  const int px = gp & 1, py = (gp >> 1) & 1, pz = (gp >> 2) & 1;
+  return (cx == px) + (cy == py) + (cz == pz);
+}
+
+// One wavefront per hexahedron, 4 per workgroup.
+//  set-up: lane (gp, n) = (lane / 8, lane % 8) takes node n at Gauss point
+//    gp: its shape-function gradient dN_n, its share x_n (x) dN_n of the
+//    Jacobian and u_n (x) g_n of H = grad u, both summed over the 8 lanes of
+//    the point by DPP; the 8 lanes of a point then evaluate the material
+//    point (the same values in each) and write g_n, h_n and the point's
+//    stress data to LDS;
+//  blocks: lane (a, b) accumulates the 3x3 block K_ab and M_ab over the 8
+//    points, takes the force share of point b on node a, and forms its
+//    blocks of A_e and b_e.  Node b's velocity is the one the lane loaded in
+//    the set-up (same b).
 template <typename T, int MAT, bool COMPACT>
 __global__ __launch_bounds__(256) void k_elem_hex(
     int64_t n_elems, const int32_t *__restrict__ conn, const uint8_t *__restrict__ slot,
@@ -208,74 +274,72 @@ __global__ __launch_bounds__(256) void k_elem_hex(
     T *__restrict__ A, double *__restrict__ bvec, T *__restrict__ ebuf,
     double *__restrict__ rbuf, PcgState *state) {
   constexpr int NW = 4;
-  __shared__ T s_x[NW][8][3], s_u[NW][8][3], s_v[NW][8][3];
   __shared__ T s_g[NW][8][8][3], s_h[NW][8][8][3];
   __shared__ T s_P[NW][8][9], s_S[NW][8][9], s_FF[NW][8][9], s_c[NW][8][4];
-  __shared__ int s_node[NW][8];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t e = (int64_t)blockIdx.x * NW + w;
   const bool valid = e < n_elems;
   const int a = lane >> 3, b = lane & 7;
+  const int64_t ec = valid ? e : 0;  // clamped: every lane runs the set-up
 
-  if (valid && lane < 8) {
-    const int nd = conn[e * 8 + lane];
-    const int n0 = conn[e * 8];
-    s_node[w][lane] = nd;
-    for (int i = 0; i < 3; ++i) {
-      s_x[w][lane][i] = (T)(X[3 * nd + i] - X[3 * n0 + i]);
-      s_u[w][lane][i] = (T)(q[3 * nd + i] - X[3 * nd + i]);
-      s_v[w][lane][i] = (T)v[3 * nd + i];
-    }
+  // node b of the element (lane (gp, n = b))
+  const int nd = conn[ec * 8 + b];
+  const int n0 = conn[ec * 8];
+  T xr[3], u[3], vb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double Xi = X[3 * nd + i];
+    xr[i] = (T)(Xi - X[3 * n0 + i]);
+    u[i] = (T)(q[3 * nd + i] - Xi);
+    vb[i] = (T)v[3 * nd + i];
   }
-  __syncthreads();
-  T Ee = valid ? (T)Ev[e] : T(0);
+  const T Ee = (T)Ev[ec];
   const T nu = (T)prm.nu;
   const T mu = Ee / (T(2) * (T(1) + nu));
   const T lam = Ee * nu / ((T(1) + nu) * (T(1) - T(2) * nu));
   const T g1 = T(0.57735026918962576451);  // 1/sqrt(3)
-  if (valid && lane < 8) {
-    const int gp = lane;
+  {
+    const int gp = a, n = b;
     const T xi[3] = {(gp & 1) ? g1 : -g1, (gp & 2) ? g1 : -g1, (gp & 4) ? g1 : -g1};
-    T dN[8][3];
-    for (int n = 0; n < 8; ++n) {
-      const T s0 = (T)c_hex_sign[n][0], s1 = (T)c_hex_sign[n][1], s2 = (T)c_hex_sign[n][2];
-      const T t0 = T(1) + s0 * xi[0], t1 = T(1) + s1 * xi[1], t2 = T(1) + s2 * xi[2];
-      dN[n][0] = T(0.125) * s0 * t1 * t2;
-      dN[n][1] = T(0.125) * s1 * t0 * t2;
-      dN[n][2] = T(0.125) * s2 * t0 * t1;
-    }
-    T J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int n = 0; n < 8; ++n)
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) J[i * 3 + j] += s_x[w][n][i] * dN[n][j];
+    const T s0 = (T)c_hex_sign[n][0], s1 = (T)c_hex_sign[n][1], s2 = (T)c_hex_sign[n][2];
+    const T t0 = T(1) + s0 * xi[0], t1 = T(1) + s1 * xi[1], t2 = T(1) + s2 * xi[2];
+    const T dN[3] = {T(0.125) * s0 * t1 * t2, T(0.125) * s1 * t0 * t2, T(0.125) * s2 * t0 * t1};
+    T J[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) J[i * 3 + j] = sum8(xr[i] * dN[j]);
     const T dJ = det3(J);
     T Ji[9];
     inv3(J, dJ, Ji);
-    T H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int n = 0; n < 8; ++n) {
-      T g[3];
-      for (int i = 0; i < 3; ++i) g[i] = dN[n][0] * Ji[0 * 3 + i] + dN[n][1] * Ji[1 * 3 + i] + dN[n][2] * Ji[2 * 3 + i];
-      for (int i = 0; i < 3; ++i) s_g[w][gp][n][i] = g[i];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) H[i * 3 + j] += s_u[w][n][i] * g[j];
-    }
+    T g[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) g[i] = dN[0] * Ji[0 * 3 + i] + dN[1] * Ji[1 * 3 + i] + dN[2] * Ji[2 * 3 + i];
+    T H[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[i * 3 + j] = sum8(u[i] * g[j]);
     T P[9], vec[9], S[9], FF[9], c[3];
     const T Jf = material_point<T, MAT>(H, mu, lam, dJ, P, vec, S, FF, c);
-    if (!(dJ > T(0)) || !(Jf > T(0))) atomicOr(&state->elem_status, 1);
-    for (int i = 0; i < 9; ++i) {
-      s_P[w][gp][i] = P[i];
-      s_S[w][gp][i] = S[i];
-      s_FF[w][gp][i] = FF[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      s_g[w][gp][n][i] = g[i];
+      s_h[w][gp][n][i] = vec[i * 3] * g[0] + vec[i * 3 + 1] * g[1] + vec[i * 3 + 2] * g[2];
     }
-    s_c[w][gp][0] = c[0];
-    s_c[w][gp][1] = c[1];
-    s_c[w][gp][2] = c[2];
-    s_c[w][gp][3] = dJ;
-    for (int n = 0; n < 8; ++n)
-      for (int i = 0; i < 3; ++i) {
-        const T *gg = s_g[w][gp][n];
-        s_h[w][gp][n][i] = vec[i * 3] * gg[0] + vec[i * 3 + 1] * gg[1] + vec[i * 3 + 2] * gg[2];
+    if (n == 0) {
+      if (valid && (!(dJ > T(0)) || !(Jf > T(0)))) atomicOr(&state->elem_status, 1);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        s_P[w][gp][i] = P[i];
+        s_S[w][gp][i] = S[i];
+        s_FF[w][gp][i] = FF[i];
       }
+      s_c[w][gp][0] = c[0];
+      s_c[w][gp][1] = c[1];
+      s_c[w][gp][2] = c[2];
+      s_c[w][gp][3] = dJ;
+    }
   }
   __syncthreads();
   if (!valid) return;
@@ -283,14 +347,11 @@ __global__ __launch_bounds__(256) void k_elem_hex(
   T K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   T Mab = 0;
   const T rho = (T)prm.rho;
+#pragma unroll
   for (int gp = 0; gp < 8; ++gp) {
     add_kab<T, MAT>(K, s_g[w][gp][a], s_g[w][gp][b], s_h[w][gp][a], s_h[w][gp][b], s_S[w][gp],
                     s_FF[w][gp], s_c[w][gp]);
-    const T xi0 = (gp & 1) ? g1 : -g1, xi1 = (gp & 2) ? g1 : -g1, xi2 = (gp & 4) ? g1 : -g1;
-    const T Na = T(0.125) * (T(1) + (T)c_hex_sign[a][0] * xi0) * (T(1) + (T)c_hex_sign[a][1] * xi1) *
-                 (T(1) + (T)c_hex_sign[a][2] * xi2);
-    const T Nb = T(0.125) * (T(1) + (T)c_hex_sign[b][0] * xi0) * (T(1) + (T)c_hex_sign[b][1] * xi1) *
-                 (T(1) + (T)c_hex_sign[b][2] * xi2);
+    const T Na = (T)c_hex_N[hex_agree(a, gp)], Nb = (T)c_hex_N[hex_agree(b, gp)];
     Mab += rho * Na * Nb * s_c[w][gp][3];
   }
   // force share: Gauss point b of node a
@@ -302,7 +363,6 @@ __global__ __launch_bounds__(256) void k_elem_hex(
   }
   const T h = (T)prm.h, al = (T)prm.alpha, be = (T)prm.beta;
   const T cM = T(1) + h * al, cK = h * (be + h), cKv = be + h;
-  const T *vb = s_v[w][b];
   const T grav[3] = {(T)prm.gx, (T)prm.gy, (T)prm.gz};
   T Ablk[9], rhs[3];
   for (int i = 0; i < 3; ++i) {
@@ -314,8 +374,9 @@ __global__ __launch_bounds__(256) void k_elem_hex(
     Ablk[i * 4] += cM * Mab;
     rhs[i] = Mab * grav[i] - fa[i] - al * Mab * vb[i] - cKv * kv;
   }
-  scatter<T, COMPACT, 8>(e, a, b, s_node[w][a], Ablk, rhs, slot, smap, row_ptr, dof_fixed, A,
-                         bvec, ebuf, rbuf);
+  const int ga = COMPACT ? 0 : conn[e * 8 + a];
+  scatter<T, COMPACT, 8>(e, a, b, ga, Ablk, rhs, slot, smap, row_ptr, dof_fixed, A, bvec, ebuf,
+                         rbuf);
 }
 
 // ---------------------------------------------- Mooney-Rivlin, co-rotational
@@ -909,9 +970,20 @@ __global__ void k_assembly_gather(int64_t n_blocks, const int32_t *__restrict__ 
   double br[3] = {0, 0, 0};
   for (int32_t j = blk_ptr[k]; j < blk_ptr[k + 1]; ++j) {
     const int32_t src = blk_src[j];
-    const T *eb = ebuf + (int64_t)src * 9;
+    // src = e * NEN^2 + a * NEN + b; block (a, b) of element e is stored as
+    // such when a <= b, else as the transpose of block (b, a)
+    const int32_t e = src / (NEN * NEN), ab = src % (NEN * NEN);
+    const int a = ab / NEN, bb = ab % NEN;
+    const bool tr = a > bb;
+    const T *eb = ebuf + ((int64_t)e * (NEN * (NEN + 1) / 2) +
+                          (tr ? sym_block<NEN>(bb, a) : sym_block<NEN>(a, bb))) * 9;
+    T blk[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] += (double)eb[q];
+    for (int q = 0; q < 9; ++q) blk[q] = eb[q];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[r * 3 + c] += (double)(tr ? blk[c * 3 + r] : blk[r * 3 + c]);
     if (diag) {
       // src = e * NEN^2 + a * NEN + a: the RHS share of node a of element e
       const int64_t ea = (int64_t)(src / (NEN * NEN)) * NEN + (src % (NEN * NEN)) / NEN;

@@ -1,0 +1,72 @@
+"""Initial guesses of the step's CG (the paper leaves x0 open; x0 = 0 by
+default): the previous acceleration, and the A-norm projection of the
+solution onto the last m accelerations.  Any x0 leads to a solution meeting
+the same recomputed-residual test, so the trajectory must match the
+oracle's direct-solve rollout as with x0 = 0; the projection must not need
+more iterations than x0 = 0 once its history is filled, and with m >= 2 it
+reproduces a solution that lies in the span exactly (the iteration count of
+a repeated identical step drops to zero)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import step as ostep
+
+pytestmark = pytest.mark.gpu
+
+from paper_2306_05893_amd import FE_PREC_FP64, FE_PREC_MIXED  # noqa: E402
+from paper_2306_05893_amd.sim import StepOptions, Simulation  # noqa: E402
+
+
+@pytest.mark.parametrize("warm", [1, 2, 8])
+@pytest.mark.parametrize("prec", [FE_PREC_FP64, FE_PREC_MIXED])
+def test_trajectory_with_initial_guess(prec, warm):
+    w = synth.make("hex_diff")
+    n = 8
+    print(f"[warm] hex_diff prec={prec} warm_start={warm}", flush=True)
+    qo, vo = ostep.rollout(w, w.q0(), w.v0(), n, solver="banded")[-1]
+    its = {}
+    for ws in (0, warm):
+        sim = Simulation(w, prec=prec, factor_on_gpu=True)
+        opts = StepOptions(rel_tol=1e-10, max_it=500, refresh=4, lag=0, warm_start=ws)
+        its[ws] = []
+        for _ in range(n):
+            st = sim.step(opts)
+            assert st.solve.status == 0 and st.solve.rel_res <= 1e-10
+            its[ws].append(st.solve.iterations)
+        torch.cuda.synchronize()
+        q = sim.q.cpu().numpy()
+        eq = np.linalg.norm(q - qo) / np.linalg.norm(qo - w.q0())
+        print(f"  warm_start={ws}: iterations {its[ws]}, displacement rel err {eq:.2e}")
+        assert eq <= (1e-8 if prec == FE_PREC_FP64 else 1e-5)
+        sim.ctx.close()
+    # once the history holds earlier solutions the guess is never worse
+    assert sum(its[warm][2:]) <= sum(its[0][2:])
+
+
+@pytest.mark.parametrize("warm", [1, 4])
+@pytest.mark.parametrize("prec", [FE_PREC_FP64, FE_PREC_MIXED])
+def test_repeated_step_starts_at_its_solution(prec, warm):
+    # The same step taken twice from the same state: A and b are the same
+    # bit for bit (the assembly sums in a fixed order) and the first
+    # solution a1 met the recomputed-residual test.  warm_start = 1 starts
+    # the second solve at a1, which passes the test at once (0 iterations).
+    # The projection (m = 4) starts at the A-norm best approximation in a
+    # span that contains a1, whose residual is within sqrt(cond A) of a1's;
+    # a fresh factor every step then finishes in at most 2 iterations.
+    w = synth.make("hex_diff")
+    sim = Simulation(w, prec=prec, factor_on_gpu=True)
+    opts = StepOptions(rel_tol=1e-8, max_it=500, refresh=1, lag=0, warm_start=warm)
+    for _ in range(3):
+        sim.step(opts)
+    q, v = sim.q.clone(), sim.v.clone()
+    st1 = sim.step(opts)
+    sim.q.copy_(q)
+    sim.v.copy_(v)
+    st2 = sim.step(opts)
+    print(f"[warm] repeated step prec={prec} warm_start={warm}: iterations "
+          f"{st1.solve.iterations} then {st2.solve.iterations} (rel-res {st2.solve.rel_res:.1e})")
+    assert st1.solve.iterations >= 1 and st2.solve.rel_res <= 1e-8
+    assert st2.solve.iterations == 0 if warm == 1 else st2.solve.iterations <= 2
+    sim.ctx.close()

@@ -51,6 +51,9 @@ HEADLINE = "hex_block"
 # initial guess of the timed steps' CG: the A-norm projection onto the last
 # 8 accelerations (x0 = 0 is timed beside it)
 HEADLINE_WARM = 8
+# the stale factor rotated to the current state (P^-1 = Q A_t0^-1 Q^T, per-node
+# rotations); the plain stale factor is timed beside it
+HEADLINE_ROTATE = 1
 
 
 def _free(sim):
@@ -60,7 +63,7 @@ def _free(sim):
     torch.cuda.empty_cache()
 
 
-def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True, warm_start=0):
+def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True, warm_start=0, rotate=0):
     import torch
 
     from paper_2306_05893_amd import FE_FACTOR_ASYNC, FE_FACTOR_DETERMINISTIC
@@ -68,9 +71,9 @@ def _timed_run(w, prec, steps, warmup, timing=False, gpu_factor=True, warm_start
 
     sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=gpu_factor)
     det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
-                   mode=FE_FACTOR_DETERMINISTIC, warm_start=warm_start)
+                   mode=FE_FACTOR_DETERMINISTIC, warm_start=warm_start, rotate=rotate)
     asy = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0, mode=FE_FACTOR_ASYNC,
-                   warm_start=warm_start)
+                   warm_start=warm_start, rotate=rotate)
     for _ in range(warmup):
         sim.step(det)
     torch.cuda.synchronize()
@@ -201,7 +204,7 @@ def _kernel_pass_only(workload, n_apply):
                       "roofline": _roofline(kt, workload)}))
 
 
-def _adjoint_leg(w, prec, nsteps, k, warm_start=0):
+def _adjoint_leg(w, prec, nsteps, k, warm_start=0, rotate=0):
     """The full differentiable configuration: a target rollout with the
     second E field, then a rollout of nsteps forward steps with checkpoints
     every k steps (timed: forward steps/s) and its adjoint (timed: reverse
@@ -217,7 +220,7 @@ def _adjoint_leg(w, prec, nsteps, k, warm_start=0):
     A, _ = sim.ctx.assemble(sim.params, sim.q, sim.v)
     sim.ctx.factorize_now(A, 0)
     opts = sim.opts(rel_tol=w.rel_tol, max_it=3000, refresh=w.refresh, lag=0,
-                    mode=FE_FACTOR_ASYNC, warm_start=warm_start)
+                    mode=FE_FACTOR_ASYNC, warm_start=warm_start, rotate=rotate)
     q0, v0 = sim.q.clone(), sim.v.clone()
     E_t = torch.as_tensor(w.extra["E_target"], dtype=torch.float64, device="cuda")
     with torch.no_grad():
@@ -251,7 +254,8 @@ def _headline(steps, warmup, extras, kernel_applies):
 
     w = synth.make(HEADLINE)
     _log(f"[bench] {HEADLINE}: {w.n_dofs} DOFs, {w.n_elems} elements")
-    mixed = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=HEADLINE_WARM)
+    mixed = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=HEADLINE_WARM,
+                       rotate=HEADLINE_ROTATE)
     _log(f"[bench] {HEADLINE} mixed {mixed['steps_per_s']:.2f} steps/s "
           f"it={mixed['cg_it_mean']:.1f} lag={mixed['factor_lag_mean']:.1f}")
     sizes = mixed["sim"].ctx.sizes
@@ -260,18 +264,20 @@ def _headline(steps, warmup, extras, kernel_applies):
     _free(mixed.pop("sim"))
     out = {"w": w, "mixed": mixed, "sizes": sizes, "kt": kt}
     if extras:
-        fp64 = _timed_run(w, FE_PREC_FP64, steps, warmup, warm_start=HEADLINE_WARM)
+        fp64 = _timed_run(w, FE_PREC_FP64, steps, warmup, warm_start=HEADLINE_WARM,
+                          rotate=HEADLINE_ROTATE)
         _free(fp64.pop("sim"))
         out["fp64"] = fp64
         _log(f"[bench] {HEADLINE} fp64 {fp64['steps_per_s']:.2f} steps/s "
               f"it={fp64['cg_it_mean']:.1f}")
-        zero = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=0)
+        zero = _timed_run(w, FE_PREC_MIXED, steps, warmup, warm_start=0, rotate=0)
         _free(zero.pop("sim"))
         out["mixed_x0_zero"] = zero
-        _log(f"[bench] {HEADLINE} mixed, x0 = 0: {zero['steps_per_s']:.2f} steps/s "
+        _log(f"[bench] {HEADLINE} mixed, plain stale factor, x0 = 0: "
+             f"{zero['steps_per_s']:.2f} steps/s "
               f"it={zero['cg_it_mean']:.1f}")
         adj = _adjoint_leg(w, FE_PREC_MIXED, w.steps, w.extra["checkpoint_every"],
-                           warm_start=HEADLINE_WARM)
+                           warm_start=HEADLINE_WARM, rotate=HEADLINE_ROTATE)
         out["adjoint"] = adj
         _log(f"[bench] {HEADLINE} {w.steps} forward steps {adj['forward_steps_per_s']} steps/s, "
               f"adjoint {adj['adjoint_steps_per_s']} steps/s")
@@ -562,10 +568,11 @@ def _age_curve(workload, nsteps, variants):
            "variants": {}}
     for tag in variants:
         prec = FE_PREC_FP64 if tag.startswith("fp64") else FE_PREC_MIXED
-        warm = 1 if tag.endswith("warm") else (int(tag.split("proj")[1]) if "proj" in tag else 0)
+        warm = 1 if "warm" in tag else (int(tag.split("proj")[1][:1]) if "proj" in tag else 0)
+        rot = 1 if tag.endswith("rot") else 0
         sim = Simulation(w, prec=prec, device="cuda", factor_on_gpu=True)
         det = sim.opts(rel_tol=1e-8, max_it=3000, refresh=w.refresh, lag=0,
-                       mode=FE_FACTOR_DETERMINISTIC, warm_start=warm)
+                       mode=FE_FACTOR_DETERMINISTIC, warm_start=warm, rotate=rot)
         ages, its, ms = [], [], []
         for k in range(nsteps):
             torch.cuda.synchronize()
@@ -813,7 +820,7 @@ def main():
         return
     if args.age_curve > 0:
         _age_curve(args.workload, args.age_curve,
-                   ("mixed", "mixed_warm", "mixed_proj8", "fp64"))
+                   ("mixed", "mixed_rot", "mixed_proj8", "mixed_proj8_rot", "fp64"))
         return
     if args.kernel_pass_only:
         _kernel_pass_only(args.workload, args.kernel_applies)
@@ -842,7 +849,7 @@ def main():
             "fp64_cg_it_mean": round(fp64["cg_it_mean"], 2),
             "fp64_factor_lag_mean": round(fp64["factor_lag_mean"], 1),
             "mixed_vs_fp64": round(mixed["steps_per_s"] / fp64["steps_per_s"], 3),
-            "mixed_x0_zero": _leg(h["mixed_x0_zero"]),
+            "mixed_plain_x0_zero": _leg(h["mixed_x0_zero"]),
             "adjoint_steps_per_s": h["adjoint"]["adjoint_steps_per_s"],
             "full_config": h["adjoint"],
         }
@@ -870,7 +877,11 @@ def main():
                                f"{w.n_dofs} DOFs, h=0.01, LDL^T refreshed every {w.refresh} "
                                "steps (asynchronous, FP64 factorisation on its own GPU "
                                "stream), mixed precision, rel-res 1e-8, CG initial guess "
-                               f"projected on the last {HEADLINE_WARM} accelerations",
+                               f"projected on the last {HEADLINE_WARM} accelerations"
+                               + (", stale factor rotated to the current state"
+                                  if HEADLINE_ROTATE else ""),
+                   "preconditioner": ("stale LDL^T rotated per node to the current state"
+                                      if HEADLINE_ROTATE else "stale LDL^T"),
                    "cg_initial_guess": (f"A-norm projection on the last {HEADLINE_WARM} "
                                         "accelerations" if HEADLINE_WARM >= 2 else
                                         "previous acceleration" if HEADLINE_WARM == 1 else

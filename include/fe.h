@@ -168,7 +168,16 @@ typedef struct {
                                  per step; vectors that are nearly
                                  combinations of newer ones are dropped).
                                  Values above 8 use 8.                        */
-  int32_t pad_;
+  int32_t rotate_precond;     /* 1: apply the stale factor rotated to the
+                                 current state, P^{-1} = Q A_t0^{-1} Q^T with
+                                 Q_n = R_n(t) R_n(t0)^T per node (R_n: the
+                                 rotation of the polar decomposition of the
+                                 summed element-centre deformation gradients
+                                 around node n; Q_n = I on nodes with a fixed
+                                 DOF).  Not in the paper: a correction of the
+                                 asynchronous preconditioner for bodies that
+                                 rotate; still symmetric positive definite, so
+                                 the results meet the same test.  0: off.     */
 } fe_step_opts;
 
 typedef struct {

@@ -72,7 +72,7 @@ class fe_solve_stats(C.Structure):
 class fe_step_opts(C.Structure):
     _fields_ = [("rel_tol", C.c_double), ("max_it", C.c_int32), ("refresh", C.c_int32),
                 ("lag", C.c_int32), ("mode", C.c_int32), ("warm_start", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("rotate_precond", C.c_int32)]
 
 
 class fe_step_stats(C.Structure):

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HOST_SOURCES = ["host_pattern.cpp", "host_analyse.cpp", "host_factor.cpp", "host_gpuplan.cpp"]
 HIP_SOURCES = ["kernels_element.hip", "kernels_solve.hip", "kernels_adjoint.hip",
-               "kernels_factor.hip", "kernels_multi.hip", "kernels_guess.hip", "fe_api.hip"]
+               "kernels_factor.hip", "kernels_multi.hip", "kernels_guess.hip",
+               "kernels_rotation.hip", "fe_api.hip"]
 
 CXX = shutil.which("g++") or "g++"
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"

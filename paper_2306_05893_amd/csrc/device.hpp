@@ -178,6 +178,22 @@ void launch_hist_guess(hipStream_t st, int64_t n, int m, int newest, const int32
                        const double *b, double *part, double *coef, double *x);
 void launch_hist_push(hipStream_t st, int64_t n, int slot, const double *x, double *V);
 int64_t hist_part_doubles();
+
+// Rotation of the stale preconditioner: per-node rotations R_n of state q
+// (S: 9 FP64 accumulators per node, zero on entry and cleared again), the
+// identity, Q_n = R_n(t) R_n(t0)^T, and the sweep input w = Q^T r / output
+// z = Q z per node.
+void launch_node_rotations(hipStream_t st, int elem_type, int64_t n_elems, const int32_t *conn,
+                           const double *X, const double *q, int64_t n_nodes,
+                           const uint8_t *dof_fixed, double *S, double *Rn);
+void launch_rot_identity(hipStream_t st, int64_t n_nodes, double *R);
+template <typename T>
+void launch_rot_q(hipStream_t st, int64_t n_nodes, const double *Rt, const double *R0, T *Q);
+template <typename T>
+void launch_rot_in(hipStream_t st, int64_t n_nodes, const T *Q, const double *r, T *w,
+                   const PcgState *s);
+template <typename T>
+void launch_rot_out(hipStream_t st, int64_t n_nodes, const T *Q, double *z, const PcgState *s);
 void launch_integrate(hipStream_t st, int64_t n, double h, const double *a, double *q,
                       double *v);
 

@@ -53,8 +53,9 @@ struct Timing {
 struct GraphKey {
   const void *A, *x;
   int slot, tsize;
+  bool rot;
   bool operator==(const GraphKey &o) const {
-    return A == o.A && x == o.x && slot == o.slot && tsize == o.tsize;
+    return A == o.A && x == o.x && slot == o.slot && tsize == o.tsize && rot == o.rot;
   }
 };
 
@@ -156,6 +157,15 @@ struct fe_ctx {
   // ring of earlier step solutions for the projected initial guess
   double *d_histV = nullptr, *d_histW = nullptr, *d_histP = nullptr;
   int hist_count = 0, hist_next = 0;
+  // rotation of the stale factor: node accumulators, rotations of the
+  // current state, of the state of each factor job (two, alternating) and of
+  // the factor in each slot; Q = R_now R_slot^T in the context precision
+  double *d_rotS = nullptr, *d_Rnow = nullptr, *d_Rjob[2] = {nullptr, nullptr},
+         *d_Rslot[2] = {nullptr, nullptr};
+  void *d_rotQ = nullptr;
+  bool rot_valid = false;  // d_Rnow holds the rotations of this step's state
+  bool rot_on = false;     // the solve in progress applies Q P^{-1} Q^T
+  int job_count = 0, job_rbuf = 0, gf_rbuf = 0, ready_rbuf = 0;
 
   // ---- GPU factorisation (factor_on_gpu)
   bool gpu_factor = false;
@@ -201,7 +211,7 @@ namespace {
 
 // ------------------------------------------------------------- layout
 struct Layout {
-  static constexpr int kMax = 64;
+  static constexpr int kMax = 80;
   int64_t off[kMax];
   int64_t total = 0;
   int k = 0;
@@ -220,7 +230,8 @@ enum {
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
   L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF,
-  L_MFT, L_MBT, L_HERR, L_MBDOF, L_HISTV, L_HISTW, L_HISTP
+  L_MFT, L_MBT, L_HERR, L_MBDOF, L_HISTV, L_HISTW, L_HISTP, L_ROTS, L_RNOW, L_RJOB0, L_RJOB1,
+  L_RSLOT0, L_RSLOT1, L_ROTQ
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -285,6 +296,9 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(n * kHist * 8);  // earlier solutions (initial-guess projection)
   L.add(n * kHist * 8);  // A times them
   L.add(hist_part_doubles() * 8);
+  const int64_t nn = n / 3;
+  for (int i = 0; i < 6; ++i) L.add(nn * 9 * 8);  // S, R_now, R_job x2, R_slot x2
+  L.add(nn * 9 * ts);                              // Q
   return L;
 }
 
@@ -378,6 +392,7 @@ void factor_main(fe_ctx *c) {
   (void)hipSetDevice(c->device);
   for (;;) {
     int64_t tag;
+    int rbuf;
     {
       std::unique_lock<std::mutex> lk(c->mu);
       c->cv.wait(lk, [&] { return c->quit || c->job_pending; });
@@ -385,6 +400,7 @@ void factor_main(fe_ctx *c) {
       c->job_pending = false;
       c->job_running = true;
       tag = c->job_tag;
+      rbuf = c->job_rbuf;
     }
     const auto t0 = std::chrono::steady_clock::now();
     std::string e;
@@ -403,6 +419,7 @@ void factor_main(fe_ctx *c) {
       if (c->prec == FE_PREC_MIXED) stage_factor<float>(c, panels, dinv);
       else stage_factor<double>(c, panels, dinv);
       c->ready_tag = tag;
+      c->ready_rbuf = rbuf;
       c->job_status = FE_OK;
       c->job_err.clear();
     } else {
@@ -434,6 +451,7 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
   const T *dinv = (const T *)c->d_dinv[slot];
   T *w = (T *)c->d_w, *y = (T *)c->d_y;
   if (!skip_prep) launch_tri_prep<T>(st, n, r, w, y, z, c->d_dof_fixed, s);
+  if (c->rot_on) launch_rot_in<T>(st, n / 3, (const T *)c->d_rotQ, r, w, s);
   const Symbolic &S = c->S;
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
@@ -446,6 +464,7 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
     launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s,
                       S.bwd_rows);
   }
+  if (c->rot_on) launch_rot_out<T>(st, n / 3, (const T *)c->d_rotQ, z, s);
 }
 
 // Workspace of the many-right-hand-side calls: an error word, then the
@@ -552,7 +571,8 @@ void cg_iteration(fe_ctx *c, const T *A, double *x, hipStream_t st) {
 // graph holds kernel nodes only (no memset/copy nodes).
 template <typename T>
 hipGraphExec_t iter_graph(fe_ctx *c, const T *A, double *x) {
-  const GraphKey key{(const void *)A, (const void *)x, c->active_slot, (int)sizeof(T)};
+  const GraphKey key{(const void *)A, (const void *)x, c->active_slot, (int)sizeof(T),
+                     c->rot_on};
   for (auto &kv : c->graphs)
     if (kv.first == key) return kv.second;
   hipGraph_t g = nullptr;
@@ -750,6 +770,7 @@ int gf_collect_locked(fe_ctx *c, bool block) {
     c->job_err.clear();
     c->ready_tag = c->gf_tag;
     c->ready_slot = c->gf_slot;
+    c->ready_rbuf = c->gf_rbuf;
   }
   return FE_OK;
 }
@@ -768,6 +789,8 @@ int install_locked(fe_ctx *c, hipStream_t st) {
     if (rc) return rc;
     if (c->ready_tag < 0 || c->ready_tag == c->installed_tag || c->ready_slot < 0) return FE_OK;
     HIP_TRY(hipStreamWaitEvent(st, c->ev_gf_done, 0));
+    HIP_TRY(hipMemcpyAsync(c->d_Rslot[c->ready_slot], c->d_Rjob[c->ready_rbuf],
+                           (size_t)(c->P.n / 3) * 72, hipMemcpyDeviceToDevice, st));
     if (c->active_slot >= 0) HIP_TRY(hipEventRecord(c->ev_slot_free[c->active_slot], st));
     c->active_slot = c->ready_slot;
     c->installed_tag = c->ready_tag;
@@ -782,6 +805,8 @@ int install_locked(fe_ctx *c, hipStream_t st) {
                          c->copy_stream));
   HIP_TRY(hipMemcpyAsync(c->d_dinv[slot], (char *)c->h_stage + pan_bytes, dinv_bytes,
                          hipMemcpyHostToDevice, c->copy_stream));
+  HIP_TRY(hipMemcpyAsync(c->d_Rslot[slot], c->d_Rjob[c->ready_rbuf], (size_t)(c->P.n / 3) * 72,
+                         hipMemcpyDeviceToDevice, c->copy_stream));
   HIP_TRY(hipEventRecord(c->ev_upload_done, c->copy_stream));
   c->upload_issued = true;
   HIP_TRY(hipStreamWaitEvent(st, c->ev_upload_done, 0));
@@ -789,6 +814,19 @@ int install_locked(fe_ctx *c, hipStream_t st) {
   c->active_slot = slot;
   c->installed_tag = c->ready_tag;
   return FE_OK;
+}
+
+// Rotations of a factor job's state (the current step's when they were
+// computed, else the identity) into the next job buffer, on the job's copy
+// stream; *rbuf receives the buffer index.
+hipError_t snap_rotations(fe_ctx *c, hipStream_t js, int *rbuf) {
+  const int rb = c->job_count++ & 1;
+  *rbuf = rb;
+  const int64_t nn = c->P.n / 3;
+  if (c->rot_valid)
+    return hipMemcpyAsync(c->d_Rjob[rb], c->d_Rnow, (size_t)nn * 72, hipMemcpyDeviceToDevice, js);
+  launch_rot_identity(js, nn, c->d_Rjob[rb]);
+  return hipGetLastError();
 }
 
 // GPU job: snapshot A on the factor stream (after the work queued on st;
@@ -802,6 +840,7 @@ int gf_start_locked(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_snap_ready, 0));
   HIP_TRY(hipMemcpyAsync(c->d_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToDevice,
                          c->factor_stream));
+  HIP_TRY(snap_rotations(c, c->factor_stream, &c->gf_rbuf));
   HIP_TRY(hipEventRecord(c->ev_snap_done, c->factor_stream));
   HIP_TRY(hipStreamWaitEvent(st, c->ev_snap_done, 0));
   HIP_TRY(hipStreamWaitEvent(c->factor_stream, c->ev_slot_free[slot], 0));
@@ -828,6 +867,7 @@ int factor_async_impl(fe_ctx *c, const void *A, int64_t tag, hipStream_t st) {
   HIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_snap_ready, 0));
   HIP_TRY(hipMemcpyAsync(c->h_Asnap, A, c->P.col_idx.size() * c->tsize, hipMemcpyDeviceToHost,
                          c->copy_stream));
+  HIP_TRY(snap_rotations(c, c->copy_stream, &c->job_rbuf));
   HIP_TRY(hipEventRecord(c->ev_snap_done, c->copy_stream));
   // later work on st may overwrite A (the next assembly): it waits for the copy
   HIP_TRY(hipStreamWaitEvent(st, c->ev_snap_done, 0));
@@ -859,6 +899,10 @@ int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step
   T *A = (T *)c->d_A;
   int rc = assemble<T>(c, p, q, v, A, c->d_b, st);
   if (rc) return rc;
+  c->rot_valid = o->rotate_precond != 0;
+  if (c->rot_valid)
+    launch_node_rotations(st, c->elem_type, c->P.n_elems, c->d_conn, c->d_X, q, n / 3,
+                          c->d_dof_fixed, c->d_rotS, c->d_Rnow);
   const int R = o->refresh, d = o->lag;
   if (R > 0 && step % R == 0) {
     bool busy;
@@ -905,7 +949,11 @@ int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step
   else if (!(ws == 1 && c->have_prev_a))
     launch_zero(st, n, x);
   fe_solve_stats ss;
+  c->rot_on = c->rot_valid && c->active_slot >= 0;
+  if (c->rot_on)
+    launch_rot_q<T>(st, n / 3, c->d_Rnow, c->d_Rslot[c->active_slot], (T *)c->d_rotQ);
   rc = pcg<T>(c, A, c->d_b, x, o->rel_tol, o->max_it, st, &ss);
+  c->rot_on = false;
   c->have_prev_a = true;
   if (ws >= 2 && (rc == FE_OK || rc == FE_ENOTCONV)) {
     launch_hist_push(st, n, c->hist_next, x, c->d_histV);
@@ -944,6 +992,10 @@ int adjoint_impl(fe_ctx *c, const double *q_n, const double *v_n, const double *
   // A at q_n (b is not needed but assembled alongside)
   int rc = assemble<T>(c, p, q_n, v_n, A, c->d_b, st);
   if (rc) return rc;
+  c->rot_valid = o && o->rotate_precond;
+  if (c->rot_valid)
+    launch_node_rotations(st, c->elem_type, c->P.n_elems, c->d_conn, c->d_X, q_n, n / 3,
+                          c->d_dof_fixed, c->d_rotS, c->d_Rnow);
   if (o && o->refresh > 0 && c->active_slot < 0) {
     // no factor yet: factor this A synchronously
     const int64_t tag = (int64_t(1) << 40) + c->step_count;
@@ -960,7 +1012,11 @@ int adjoint_impl(fe_ctx *c, const double *q_n, const double *v_n, const double *
   launch_abar(st, n, p->h, lq_in, lv_in, c->d_dof_fixed, c->d_abar);
   launch_zero(st, n, c->d_mu);
   fe_solve_stats ss;
+  c->rot_on = c->rot_valid && c->active_slot >= 0;
+  if (c->rot_on)
+    launch_rot_q<T>(st, n / 3, c->d_Rnow, c->d_Rslot[c->active_slot], (T *)c->d_rotQ);
   rc = pcg<T>(c, A, c->d_abar, c->d_mu, o ? o->rel_tol : 1e-10, o ? o->max_it : 1000, st, &ss);
+  c->rot_on = false;
   if (c->h_state->elem_status) {
     clear_elem_status(c, st);
     return c->fail(FE_EINVERTED, "inverted element in the adjoint step");
@@ -1197,6 +1253,13 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_histV = ptr_at<double>(w, L, L_HISTV);
   c->d_histW = ptr_at<double>(w, L, L_HISTW);
   c->d_histP = ptr_at<double>(w, L, L_HISTP);
+  c->d_rotS = ptr_at<double>(w, L, L_ROTS);
+  c->d_Rnow = ptr_at<double>(w, L, L_RNOW);
+  c->d_Rjob[0] = ptr_at<double>(w, L, L_RJOB0);
+  c->d_Rjob[1] = ptr_at<double>(w, L, L_RJOB1);
+  c->d_Rslot[0] = ptr_at<double>(w, L, L_RSLOT0);
+  c->d_Rslot[1] = ptr_at<double>(w, L, L_RSLOT1);
+  c->d_rotQ = w + L.off[L_ROTQ];
 
   // host-side resources
   HIP_TRY(hipHostMalloc((void **)&c->h_state, sizeof(PcgState), hipHostMallocDefault));
@@ -1257,6 +1320,14 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   HIP_TRY(up(c->d_mbtiles, S.mbwd_tiles.data(), S.mbwd_tiles.size() * sizeof(MTile)));
   HIP_TRY(up(c->d_mbdofs, S.mbwd_dofs.data(), S.mbwd_dofs.size() * 4));
   HIP_TRY(up(c->d_state, c->h_state, sizeof(PcgState)));
+  {
+    // rotation accumulators zero, rotations of jobs and slots the identity
+    const int64_t nn = P.n / 3;
+    launch_zero(st, 9 * nn, c->d_rotS);
+    for (double *R : {c->d_Rnow, c->d_Rjob[0], c->d_Rjob[1], c->d_Rslot[0], c->d_Rslot[1]})
+      launch_rot_identity(st, nn, R);
+    HIP_TRY(hipGetLastError());
+  }
   HIP_TRY(hipStreamSynchronize(st));
 
   // algorithmic bytes per sweep level (lower panel entries + indices + vectors)
@@ -1684,6 +1755,7 @@ int fe_reset(fe_ctx *c) {
   c->have_prev_a = false;
   c->hist_count = 0;
   c->hist_next = 0;
+  c->rot_valid = false;
   return FE_OK;
 }
 

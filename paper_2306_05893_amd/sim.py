@@ -35,10 +35,11 @@ class StepOptions:
     lag: int = 0
     mode: int = L.FE_FACTOR_DETERMINISTIC
     warm_start: int = 0
+    rotate: int = 0
 
     def c(self):
         return L.fe_step_opts(self.rel_tol, self.max_it, self.refresh, self.lag, self.mode,
-                              self.warm_start, 0)
+                              self.warm_start, self.rotate)
 
 
 class Params:

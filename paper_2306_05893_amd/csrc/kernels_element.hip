@@ -959,7 +959,13 @@ __global__ void k_assembly_gather(int64_t n_blocks, const int32_t *__restrict__ 
                                   const double *__restrict__ rbuf,
                                   const double *__restrict__ f_nodal, T *__restrict__ A,
                                   double *__restrict__ b) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // XCD-contiguous workgroups: the hardware hands workgroup b to XCD b % 8,
+  // so XCD x takes the x-th contiguous eighth of the node blocks, and node
+  // blocks that share elements (neighbours in the node order) read the
+  // contribution buffer through the same L2
+  const int64_t per = gridDim.x / 8;
+  const int64_t wg = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t k = wg * blockDim.x + threadIdx.x;
   if (k >= n_blocks) return;
   const int32_t info = blk_node[k];
   const int g = info & 0x7fffffff;
@@ -1096,7 +1102,8 @@ void launch_assembly_gather(hipStream_t st, int nen, int64_t n_blocks, const int
                             const int32_t *blk_node, const int32_t *row_ptr, const T *ebuf,
                             const double *rbuf, const double *f_nodal, T *A, double *b) {
   if (n_blocks <= 0) return;
-  const unsigned blocks = (unsigned)((n_blocks + 255) / 256);
+  // a multiple of 8 workgroups, see k_assembly_gather
+  const unsigned blocks = (unsigned)(((n_blocks + 255) / 256 + 7) / 8 * 8);
   if (nen == 8)
     k_assembly_gather<T, 8><<<blocks, 256, 0, st>>>(n_blocks, blk_ptr, blk_src, blk_pos, blk_node,
                                                     row_ptr, ebuf, rbuf, f_nodal, A, b);

@@ -15,6 +15,8 @@ struct SnDev {          // one supernode of the factor, as the GPU sees it
   int32_t nc, m;        // own columns, panel rows
   int64_t panel_off;    // entry offset of the m x nc column-major panel
   int64_t rows_off;     // offset into the rows array (DOF indices)
+  int32_t ld, pad;      // leading dimension of the panel (m rounded up to
+                        // a multiple of kPanelAlign)
 };
 
 struct TileDev {

@@ -254,8 +254,8 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add((int64_t)S.rows.size() * 4);
   L.add((int64_t)S.fwd_tiles.size() * (int64_t)sizeof(TileDev));
   L.add((int64_t)S.bwd_tiles.size() * (int64_t)sizeof(TileDev));
-  L.add(S.panel_entries * ts);
-  L.add(S.panel_entries * ts);
+  L.add(S.dev_panel_entries * ts);
+  L.add(S.dev_panel_entries * ts);
   L.add(n * ts);
   L.add(n * ts);
   L.add(n * 8);  // jdinv
@@ -378,13 +378,23 @@ struct TimedLaunch {
 // ------------------------------------------------------------- factor thread
 template <typename T>
 void stage_factor(fe_ctx *c, const std::vector<double> &panels, const std::vector<double> &dinv) {
+  // host panels (leading dimension m) to the device layout (leading
+  // dimension ld, the padding rows zero)
   T *dst = reinterpret_cast<T *>(c->h_stage);
-  const int64_t np = (int64_t)panels.size();
+  const std::vector<Supernode> &sn = c->S.sn;
+  const int64_t ns = (int64_t)sn.size();
   parallel_for(64, c->n_threads, [&](int64_t b, int) {
-    const int64_t lo = np * b / 64, hi = np * (b + 1) / 64;
-    for (int64_t i = lo; i < hi; ++i) dst[i] = (T)panels[i];
+    for (int64_t s = ns * b / 64; s < ns * (b + 1) / 64; ++s) {
+      const Supernode &q = sn[s];
+      for (int64_t j = 0; j < q.nc; ++j) {
+        const double *src = panels.data() + q.panel_off + j * q.m;
+        T *d = dst + q.dev_off + j * q.ld;
+        for (int64_t i = 0; i < q.m; ++i) d[i] = (T)src[i];
+        for (int64_t i = q.m; i < q.ld; ++i) d[i] = T(0);
+      }
+    }
   });
-  T *dd = dst + c->S.panel_entries;
+  T *dd = dst + c->S.dev_panel_entries;
   for (size_t i = 0; i < dinv.size(); ++i) dd[i] = (T)dinv[i];
 }
 
@@ -798,7 +808,7 @@ int install_locked(fe_ctx *c, hipStream_t st) {
   }
   if (c->ready_tag < 0 || c->ready_tag == c->installed_tag) return FE_OK;
   const int slot = c->active_slot < 0 ? 0 : 1 - c->active_slot;
-  const size_t pan_bytes = (size_t)c->S.panel_entries * c->tsize;
+  const size_t pan_bytes = (size_t)c->S.dev_panel_entries * c->tsize;
   const size_t dinv_bytes = (size_t)c->P.n * c->tsize;
   HIP_TRY(hipStreamWaitEvent(c->copy_stream, c->ev_slot_free[slot], 0));
   HIP_TRY(hipMemcpyAsync(c->d_panels[slot], c->h_stage, pan_bytes, hipMemcpyHostToDevice,
@@ -1165,7 +1175,7 @@ int fe_query(fe_ctx *c, int32_t prec, fe_sizes *o) {
   o->map_len = (int64_t)c->P.tmap.size();
   o->n_supernodes = (int64_t)c->S.sn.size();
   o->n_levels = c->S.n_levels;
-  o->factor_entries = c->S.panel_entries;
+  o->factor_entries = c->S.dev_panel_entries;
   o->factor_lower = c->S.lower_entries;
   o->factor_flops = c->S.flops;
   o->ws_bytes = L.total;
@@ -1270,7 +1280,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
     HIP_TRY(hipHostMalloc(&c->h_Asnap, std::max<size_t>(1, c->P.col_idx.size() * c->tsize),
                           hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(&c->h_stage,
-                          std::max<size_t>(1, (c->S.panel_entries + c->P.n) * c->tsize),
+                          std::max<size_t>(1, (c->S.dev_panel_entries + c->P.n) * c->tsize),
                           hipHostMallocDefault));
   }
   HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
@@ -1306,7 +1316,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   HIP_TRY(up(c->d_X, c->X.data(), c->X.size() * 8));
   std::vector<SnDev> sn(S.sn.size());
   for (size_t s = 0; s < S.sn.size(); ++s)
-    sn[s] = SnDev{S.sn[s].nc, S.sn[s].m, S.sn[s].panel_off, S.sn[s].rows_off};
+    sn[s] = SnDev{S.sn[s].nc, S.sn[s].m, S.sn[s].dev_off, S.sn[s].rows_off, S.sn[s].ld, 0};
   HIP_TRY(up(c->d_sn, sn.data(), sn.size() * sizeof(SnDev)));
   HIP_TRY(up(c->d_rows, S.rows.data(), S.rows.size() * 4));
   std::vector<TileDev> ft(S.fwd_tiles.size()), bt(S.bwd_tiles.size());

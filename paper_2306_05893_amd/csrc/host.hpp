@@ -78,10 +78,20 @@ std::string build_pattern(int32_t n_nodes, int32_t n_elems, int32_t nen,
                           const int32_t *conn, const uint8_t *fixed_dof, Pattern &P);
 
 // ------------------------------------------------- ordering and symbolic
+// Device panels store column j of supernode s at dev_off + j * ld with ld a
+// multiple of kPanelAlign entries, so that the sweeps' 256-row column runs of
+// a tile start on cache-line boundaries.
+constexpr int32_t kPanelAlign = 32;
+
 struct Supernode {
   int32_t nc = 0;        // own columns (DOFs eliminated in this block)
   int32_t m = 0;         // rows of the panel: own columns first, then struct
   int64_t panel_off = 0; // offset (entries) of the m x nc column-major panel
+                         // of the host factorisation (leading dimension m)
+  int32_t ld = 0;        // leading dimension of the device panel: m rounded
+                         // up to kPanelAlign entries, so that every column
+                         // starts on a 128-byte boundary (FP32)
+  int64_t dev_off = 0;   // offset (entries) of the device panel
   int64_t rows_off = 0;  // offset into Symbolic::rows
   int32_t parent = -1;   // enclosing supernode, -1 for a root
   int32_t level = 0;     // height above the leaves (dependency level)
@@ -115,6 +125,7 @@ struct Symbolic {
   std::vector<std::vector<int32_t>> children;
   int32_t n_levels = 0;
   int64_t panel_entries = 0, lower_entries = 0;
+  int64_t dev_panel_entries = 0;  // device panels, columns padded to ld
   double flops = 0.0;
   // GPU schedules, grouped by level (forward: ascending, backward: descending)
   std::vector<Tile> fwd_tiles, bwd_tiles;
@@ -155,7 +166,8 @@ struct GfFront {
   int64_t offX;        // m x nc row-major FP64 augmented block
   int64_t offW;        // m x kGfPanel column-major FP64 panel scratch
   int64_t rows_off;    // panel rows (DOF indices), as Symbolic::rows
-  int64_t panel_off;   // output panel offset, as Supernode::panel_off
+  int64_t panel_off;   // output panel offset, as Supernode::dev_off
+  int32_t ld, pad;     // output panel leading dimension, as Supernode::ld
 };
 // Square output tile of an update, kGfStepTile (regions 0/1) or kGfTile
 // (regions 2/3) wide (L: the front's scaled lower factor, d: its pivots,

@@ -303,7 +303,7 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
   // struct sets at node level, in post-order (children before parents)
   std::vector<std::vector<int32_t>> snode_struct(ns);
   std::vector<int32_t> mark(N, -1);
-  int64_t panel = 0, lower = 0;
+  int64_t panel = 0, lower = 0, dev_panel = 0;
   double flops = 0.0;
   S.rows.clear();
   for (int32_t s = 0; s < ns; ++s) {
@@ -335,6 +335,9 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
     sn.m = (int32_t)((int64_t)S.rows.size() - sn.rows_off);
     sn.panel_off = panel;
     panel += (int64_t)sn.m * sn.nc;
+    sn.ld = (sn.m + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
+    sn.dev_off = dev_panel;
+    dev_panel += (int64_t)sn.ld * sn.nc;
     lower += (int64_t)sn.m * sn.nc - (int64_t)sn.nc * (sn.nc - 1) / 2;
     // partial LDL^T + explicit inverse of L11 + W = L21 L11^{-1}
     const double m = sn.m, nc = sn.nc, nr = sn.m - sn.nc;
@@ -343,6 +346,7 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
     snode_struct[s] = std::move(st);
   }
   S.panel_entries = panel;
+  S.dev_panel_entries = dev_panel;
   S.lower_entries = lower;
   S.flops = flops;
 

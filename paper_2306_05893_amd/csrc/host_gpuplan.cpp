@@ -40,7 +40,8 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
       f.offW = cur;
       cur += round((int64_t)sn.m * kGfPanel);
       f.rows_off = sn.rows_off;
-      f.panel_off = sn.panel_off;
+      f.panel_off = sn.dev_off;
+      f.ld = sn.ld;
       G.lvl_sn.push_back(s);
       G.parent[s] = sn.parent;
     }

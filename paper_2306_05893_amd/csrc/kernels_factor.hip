@@ -645,7 +645,7 @@ __global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_
       for (int u = 0; u < E / RP; ++u) {
         const int j = j0 + rq + RP * u;
         const double x = tile[c][rq + RP * u];
-        if (i < m && j < nc) G[(int64_t)j * m + i] = (T)(i < nc ? x : -x);
+        if (i < m && j < nc) G[(int64_t)j * f.ld + i] = (T)(i < nc ? x : -x);
       }
     }
     if (blockIdx.x == 0) {

@@ -153,7 +153,8 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
   const int fa_k = tid / TPC, fa_i = (tid % TPC) * NA;
   const int ba_j = tid >> 2, ba_k = (tid & 3) * NA;
   const int bk = tid / TPR, bj = (tid % TPR) * BV;
-  const T *Gb = G + (int64_t)min(b0 + ba_j, nc - 1) * m;  // backward: this thread's column
+  const int64_t pld = d.ld;  // column stride of the panel
+  const T *Gb = G + (int64_t)min(b0 + ba_j, nc - 1) * pld;  // backward: this thread's column
   T ra[NA], rb[BV], sc = T(1);
   unsigned amask = 0;
   bool bok = false;
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void k_msweep(const MTile *__restrict__ tiles,
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int i = b0 + fa_i + q;
-        ra[q] = G[(int64_t)jc * m + min(i, m - 1)];
+        ra[q] = G[(int64_t)jc * pld + min(i, m - 1)];
         amask |= (i < m && j < hi && (i >= nc || j <= i)) ? (1u << q) : 0u;
       }
     } else {

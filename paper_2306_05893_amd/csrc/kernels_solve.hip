@@ -296,7 +296,7 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
   const int32_t dout = rw[min(i, d.m - 1)];
   // columns of this row inside the tile (own rows stop at the diagonal)
   const int lim = !valid ? 0 : (i < d.nc ? min(ncol, i + 1 - c0) : ncol);
-  const int64_t m = d.m;
+  const int64_t m = d.ld;  // column stride
   const T *G = panels + d.panel_off + (int64_t)c0 * m + (valid ? i : 0);
   const bool full = ncol == TC && t.r0 + kFR <= d.m && (t.r0 >= d.nc || t.r0 + 1 >= c0 + TC);
   T g[TC];
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   const int j0 = t.c0 + CPW * wv;
   const int nj = max(0, min(CPW, d.nc - j0));
   const int ibeg = max(r0, j0);
-  const int64_t m = d.m;
+  const int64_t m = d.ld;  // column stride
   const T *G = panels + d.panel_off + (int64_t)min(j0, d.nc - 1) * m;
   // index loads of the inputs first (clamped, unconditional), then the panel
   // loads, then the input values

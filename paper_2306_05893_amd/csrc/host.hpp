@@ -170,13 +170,18 @@ struct GfFront {
   int32_t ld, pad;     // output panel leading dimension, as Supernode::ld
 };
 // Square output tile of an update, kGfStepTile (regions 0/1) or kGfTile
-// (regions 2/3) wide (L: the front's scaled lower factor, d: its pivots,
-// W = L D for the current panel, X: augmented block):
-//   region 0  F[i, j] -= sum_{k in panel} L[i, k] W[j, k]   k1 <= j < nc, i >= j
-//   region 1  X[i, j] -= sum_{k in panel} L[i, k] X[k, j]   k1 <= i < nc, j < k1
+// (regions 2-5; kGfStepTile where a launch would hold too few of them) wide
+// (L: the front's scaled lower factor, d: its pivots, W = L D for the
+// current panel, X: augmented block; the own columns are taken in blocks of
+// kGfBlock, [K0, Ke) the block of the panel, Ke = min(K0 + kGfBlock, nc)):
+//   region 0  F[i, j] -= sum_{k in panel} L[i, k] W[j, k]   k1 <= j < Ke, i >= j
+//   region 1  X[i, j] -= sum_{k in panel} L[i, k] X[k, j]   k1 <= i < Ke, j < k1
+//   region 4  F[i, j] -= sum_{K0 <= k < Ke} L[i, k] d_k L[j, k]   Ke <= j < nc, i >= j
+//   region 5  X[i, j] -= sum_{K0 <= k < Ke} L[i, k] X[k, j]       Ke <= i < nc, j < Ke
 //   region 2  F[i, j] -= sum_{k < nc} L[i, k] d_k L[j, k]   nc <= j <= i (Schur)
 //   region 3  X[i, j] -= sum_{k < nc} L[i, k] X[k, j]       i >= nc, j < nc
-// Regions 0/1 run after each panel step; 2/3 once the own columns are done.
+// Regions 0/1 run after each panel step, 4/5 after the last panel step of a
+// block, 2/3 once the own columns are done.
 struct GfTile {
   int32_t s, region, i0, j0;
 };
@@ -189,6 +194,9 @@ constexpr int kGfStepTile = 64; // update tile of the panel steps (K = 64:
                                 // smaller tiles, more of them in flight)
 constexpr int kGfSchurMinTiles = 1024;  // fewer large Schur tiles than this
                                         // in a level: the level uses 64-wide
+constexpr int kGfBlock = 256;  // own-column block of the panel steps (regions 4/5)
+static_assert(kGfBlock % kGfTile == 0 && kGfBlock % kGfPanel == 0,
+              "block updates cover whole tiles and whole panels");
 
 struct GfPlan {
   std::vector<GfFront> fr;                   // by supernode
@@ -209,8 +217,10 @@ struct GfPlan {
   std::vector<int32_t> step_level;           // level of each step
   std::vector<int32_t> panel_sn;             // fronts with nc > k0, per step
   std::vector<int64_t> panel_ptr;
-  std::vector<GfTile> upd;                   // update tiles (regions 0-3)
+  std::vector<GfTile> upd;                   // update tiles (regions 0-5)
   std::vector<int64_t> upd_lo, upd_hi;       // regions 0/1 of each step
+  std::vector<int64_t> blk_lo, blk_hi;       // regions 4/5 after each step (may be empty),
+  std::vector<int32_t> blk_k0, blk_tile;     //   their block start K0 and tile width
   std::vector<int64_t> schur_lo, schur_hi;   // regions 2/3 of each level
   std::vector<int32_t> schur_tile;           // their tile width (per level)
   std::vector<int32_t> lvl_step_ptr;         // steps of each level

@@ -9,6 +9,25 @@
 
 namespace fe {
 
+namespace {
+
+// Order the MFMA tiles [lo, end) of one front in super-blocks of 8 x 8 tiles
+// (super-block columns, then super-block rows, then tile columns and rows):
+// the update launches give each XCD runs of 64 consecutive tiles, which then
+// share 8 row slabs and 8 column slabs of their operands in its L2.
+void group_tiles(std::vector<GfTile> &upd, size_t lo, int32_t t) {
+  const int32_t g = 8 * t;
+  std::stable_sort(upd.begin() + lo, upd.end(), [g](const GfTile &a, const GfTile &b) {
+    if (a.region != b.region) return a.region < b.region;
+    if (a.j0 / g != b.j0 / g) return a.j0 / g < b.j0 / g;
+    if (a.i0 / g != b.i0 / g) return a.i0 / g < b.i0 / g;
+    if (a.j0 != b.j0) return a.j0 < b.j0;
+    return a.i0 < b.i0;
+  });
+}
+
+}  // namespace
+
 std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
   G = GfPlan();
   const int32_t ns = (int32_t)S.sn.size();
@@ -161,23 +180,58 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
       G.step_k0.push_back(k0);
       G.upd_lo.push_back((int64_t)G.upd.size());
       G.step_level.push_back(L);
+      const int32_t K0 = k0 / kGfBlock * kGfBlock;  // block of this panel
       for (int32_t s : by_level[L]) {
         const Supernode &sn = S.sn[s];
         if (sn.nc <= k0) continue;
         G.panel_sn.push_back(s);
         const int32_t k1 = std::min(k0 + kGfPanel, sn.nc);
         const int32_t kb = k1 - k0;
-        // the rest of the own columns (all rows below the diagonal) and the
-        // own rows of X; the Schur complement waits for the level's end
-        for (int32_t j0 = k1; j0 < sn.nc; j0 += kGfStepTile)
+        const int32_t ke = std::min(K0 + kGfBlock, sn.nc);
+        // the rest of the block's own columns (all rows below the diagonal)
+        // and own rows of X; the columns and rows past the block wait for
+        // the block's end, the Schur complement for the level's end
+        for (int32_t j0 = k1; j0 < ke; j0 += kGfStepTile)
           for (int32_t i0 = j0; i0 < sn.m; i0 += kGfStepTile) G.upd.push_back({s, 0, i0, j0});
-        for (int32_t i0 = k1; i0 < sn.nc; i0 += kGfStepTile)
+        for (int32_t i0 = k1; i0 < ke; i0 += kGfStepTile)
           for (int32_t j0 = 0; j0 < k1; j0 += kGfStepTile) G.upd.push_back({s, 1, i0, j0});
         const double t = sn.nc - k1;
         flops += 2.0 * kb * (t * (sn.m - k1 - t / 2.0) + t * k1);
       }
       G.panel_ptr.push_back((int64_t)G.panel_sn.size());
       G.upd_hi.push_back((int64_t)G.upd.size());
+      // after the block's last panel step: the block applied to the own
+      // columns and own rows of X past it (K = kGfBlock), in fronts that
+      // have own columns past it
+      G.blk_lo.push_back((int64_t)G.upd.size());
+      G.blk_k0.push_back(K0);
+      int32_t bt = kGfTile;
+      if ((k0 + kGfPanel) % kGfBlock == 0) {
+        const int32_t ke = K0 + kGfBlock;
+        auto block_tiles = [&](int32_t t) {
+          int64_t n = 0;
+          for (int32_t s : by_level[L]) {
+            const Supernode &sn = S.sn[s];
+            if (sn.nc <= ke) continue;
+            const int64_t c = (sn.nc - ke + t - 1) / t, r = (sn.m - ke + t - 1) / t;
+            n += c * r - c * (c - 1) / 2 + c * (ke / t);
+          }
+          return n;
+        };
+        bt = block_tiles(kGfTile) >= kGfSchurMinTiles ? kGfTile : kGfStepTile;
+        for (int32_t s : by_level[L]) {
+          const Supernode &sn = S.sn[s];
+          if (sn.nc <= ke) continue;
+          const size_t lo = G.upd.size();
+          for (int32_t j0 = ke; j0 < sn.nc; j0 += bt)
+            for (int32_t i0 = j0; i0 < sn.m; i0 += bt) G.upd.push_back({s, 4, i0, j0});
+          for (int32_t i0 = ke; i0 < sn.nc; i0 += bt)
+            for (int32_t j0 = 0; j0 < ke; j0 += bt) G.upd.push_back({s, 5, i0, j0});
+          group_tiles(G.upd, lo, bt);
+        }
+      }
+      G.blk_tile.push_back(bt);
+      G.blk_hi.push_back((int64_t)G.upd.size());
     }
     // Schur complement and struct rows of X, one pass each (K = nc), on
     // kGfTile tiles, or kGfStepTile tiles when the level has too few of the
@@ -195,10 +249,12 @@ std::string gpu_plan(const Pattern &P, const Symbolic &S, GfPlan &G) {
     G.schur_lo.push_back((int64_t)G.upd.size());
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
+      const size_t lo = G.upd.size();
       for (int32_t j0 = sn.nc; j0 < sn.m; j0 += st)
         for (int32_t i0 = j0; i0 < sn.m; i0 += st) G.upd.push_back({s, 2, i0, j0});
       for (int32_t i0 = sn.nc; i0 < sn.m; i0 += st)
         for (int32_t j0 = 0; j0 < sn.nc; j0 += st) G.upd.push_back({s, 3, i0, j0});
+      group_tiles(G.upd, lo, st);
       const double r = sn.m - sn.nc, c = sn.nc;
       flops += r * r * c + r * c * c;
     }

@@ -12,7 +12,12 @@
 //            the block to the rows below it (one thread per row, panel
 //            values in registers) and its row operations to the panel rows
 //            of X (one thread per column); then 64 x 64 FP64 FMA tiles
-//            update the remaining own columns of F and the own rows of X
+//            update the rest of the panel's 256-column block of F and the
+//            block's own rows of X
+//   blocks   after the last panel of a 256-column block: the block applied
+//            to the own columns and own rows of X past it, in one pass
+//            (K = 256) on the matrix cores, so that the trailing own columns
+//            are read and written once per block rather than once per panel
 //   schur    once the own columns are done: the Schur complement
 //            F22 -= L21 D L21^T and the struct rows of X, -L21 X_own, in one
 //            pass over each 128 x 128 output tile (K = nc; 64 x 64 on the
@@ -458,8 +463,8 @@ __device__ void gf_update(const GfTile t, const GfFront f, int k0, double *base)
 // An MFMA block's result holds, in register q of lane l, column l % 16 of
 // row 4q + l / 16, so the instruction is oriented per region so that the 16
 // lanes of a register run along the output's contiguous index: rows i for
-// the column-major F and U outputs (regions 0 and 2), columns j for the
-// row-major X outputs (regions 1 and 3).  "fast" below is that index,
+// the column-major F and U outputs (regions 0, 2 and 4), columns j for the
+// row-major X outputs (regions 1, 3 and 5).  "fast" below is that index,
 // "slow" the other one; the slow operand is negated, so that each MFMA
 // subtracts its product from the accumulators.
 typedef double gf_d4 __attribute__((ext_vector_type(4)));
@@ -477,8 +482,12 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
     kbeg = k0, kend = min(k0 + NB, nc), imax = nc, jmax = kend;
   } else if (reg == 2) {
     kbeg = 0, kend = nc, imax = m, jmax = m;
-  } else {
+  } else if (reg == 3) {
     kbeg = t.j0, kend = nc, imax = m, jmax = nc;  // X[k, j] = 0 for k < j
+  } else if (reg == 4) {
+    kbeg = k0, kend = min(k0 + kGfBlock, nc), imax = m, jmax = nc;  // k0: the block start
+  } else {
+    kbeg = max(k0, t.j0), kend = min(k0 + kGfBlock, nc), imax = nc, jmax = nc;
   }
   double *F = base + f.offF;
   double *X = base + f.offX;
@@ -488,7 +497,8 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
   __shared__ double sA[KC][TL + 2];
   __shared__ double sB[KC][TL + 2];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const bool fout = reg == 0 || reg == 2;
+  const bool fout = reg == 0 || reg == 2 || reg == 4;  // column-major F or U output
+  const bool fl = reg == 0 || reg == 4;                // F output
   // quadrant of this wavefront and the output index of each accumulator
   const int wf = (wv & 1) * (TL / 2), ws = (wv >> 1) * (TL / 2);
   const int fbase = fout ? t.i0 : t.j0, sbase = fout ? t.j0 : t.i0;
@@ -504,7 +514,7 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
         const int fi = min(fbase + wf + 16 * fb + lf, fmax - 1);
         const int si = min(sbase + ws + 16 * sb + 4 * q + ls, smax - 1);
         double v;
-        if (reg == 0) v = F[(int64_t)si * m + fi];
+        if (fl) v = F[(int64_t)si * m + fi];
         else if (reg == 2) v = U[(si - nc) * ru + (fi - nc)];
         else v = X[(int64_t)si * nc + fi];
         acc[sb][fb][q] = v;
@@ -533,7 +543,7 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
       if (reg == 0) {
 #pragma unroll
         for (int q = 0; q < QH; ++q) b[q] = W[(int64_t)(kk[q] - k0) * m + sj_];
-      } else if (reg == 2) {
+      } else if (reg == 2 || reg == 4) {
         double dk[QH];
 #pragma unroll
         for (int q = 0; q < QH; ++q) {
@@ -580,7 +590,7 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
         const int i = fout ? fi : si, j = fout ? si : fi;
         if (i >= imax || j >= jmax) continue;
         const double v = acc[sb][fb][q];
-        if (reg == 0) {
+        if (fl) {
           if (i >= j) F[(int64_t)j * m + i] = v;
         } else if (reg == 2) {
           if (i >= j) U[(j - nc) * ru + (i - nc)] = v;
@@ -590,11 +600,29 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
       }
 }
 
+// Tile of workgroup blockIdx.x in the round of gridDim.x tiles starting at
+// r0.  The hardware hands workgroup b to XCD b % 8, the XCD's k-th being
+// b = 8 k + x; in a full round of 512-tile spans, XCD x takes tiles
+// 64 x .. 64 x + 63 of each span in turn, so the tiles in flight on one XCD
+// (two per CU) are 64 consecutive tiles of the list, which the plan orders
+// in 8 x 8 super-blocks of a front.  The rest of the round keeps the plain
+// order.
+__device__ inline int64_t gf_tile_of(int64_t r0, int64_t n_tiles) {
+  const int64_t g = gridDim.x / 512 * 512, b = blockIdx.x;
+  if (b < g && r0 + g <= n_tiles) {
+    const int64_t k = b / 8;
+    return r0 + (k / 64) * 512 + (b % 8) * 64 + k % 64;
+  }
+  return r0 + b;
+}
+
+// Two workgroups per CU (their LDS stages fit together): one's loads overlap
+// the other's matrix work.
 template <int TL>
-__global__ __launch_bounds__(256) void k_gf_update_mfma(const GfTile *tiles, int64_t n_tiles,
-                                                        const GfFront *fr, int k0, double *base) {
-  for (int64_t q = blockIdx.x; q < n_tiles; q += gridDim.x) {
-    const GfTile t = tiles[q];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gf_update_mfma(
+    const GfTile *tiles, int64_t n_tiles, const GfFront *fr, int k0, double *base) {
+  for (int64_t r0 = 0; r0 + blockIdx.x < n_tiles; r0 += gridDim.x) {
+    const GfTile t = tiles[gf_tile_of(r0, n_tiles)];
     gf_update_mfma<TL>(t, fr[t.s], k0, base);
     __syncthreads();
   }
@@ -716,6 +744,13 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
       const int64_t u0 = P.upd_lo[s], nu = P.upd_hi[s] - u0;
       if (nu > 0)
         k_gf_update<kGfStepTile><<<grid1(nu), 256, 0, st>>>(d.upd + u0, nu, d.fr, k0, d.fronts);
+      const int64_t b0 = P.blk_lo[s], nb = P.blk_hi[s] - b0;
+      if (nb > 0 && P.blk_tile[s] == kGfTile)
+        k_gf_update_mfma<kGfTile><<<grid1(nb), 256, 0, st>>>(d.upd + b0, nb, d.fr, P.blk_k0[s],
+                                                             d.fronts);
+      else if (nb > 0)
+        k_gf_update_mfma<kGfStepTile><<<grid1(nb), 256, 0, st>>>(d.upd + b0, nb, d.fr,
+                                                                 P.blk_k0[s], d.fronts);
     }
     const int64_t h0 = P.schur_lo[L], nh = P.schur_hi[L] - h0;
     if (nh > 0 && P.schur_tile[L] == kGfTile)

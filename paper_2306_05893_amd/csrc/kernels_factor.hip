@@ -471,7 +471,7 @@ typedef double gf_d4 __attribute__((ext_vector_type(4)));
 
 template <int TL>
 __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *base) {
-  constexpr int KC = 32;
+  constexpr int KC = 16;
   constexpr int NBK = TL / 32;  // 16 x 16 blocks per wavefront quadrant edge
   const int m = f.m, nc = f.nc;
   const int reg = t.region;
@@ -519,56 +519,64 @@ __device__ void gf_update_mfma(const GfTile t, const GfFront f, int k0, double *
         else v = X[(int64_t)si * nc + fi];
         acc[sb][fb][q] = v;
       }
-  // staging as in gf_update
-  constexpr int KS = 256 / TL;
-  constexpr int NPASS = 4;
-  constexpr int QH = KC / KS / NPASS;
+  // Staging: thread (sr, kq) holds column sr of the rows k = kq + KS q of
+  // both operands.  The whole next chunk is fetched into registers while
+  // the current one is multiplied out of LDS (the loads are clamped into the
+  // range and unconditional; the rows past the range are zeroed when written
+  // to LDS), so a chunk's loads are in flight for a chunk's worth of matrix
+  // work.  For the L D L^T products (regions 2 and 4) the pivots d_k of the
+  // chunk go to sD and scale the slow operand as it is read.
+  constexpr int KS = 256 / TL;  // k rows per pass of the block
+  constexpr int QN = KC / KS;   // staged entries per thread and operand
   const int sr = tid % TL, kq = tid / TL;
   const bool iok = t.i0 + sr < imax, jok = t.j0 + sr < jmax;
   const int si_ = min(t.i0 + sr, imax - 1), sj_ = min(t.j0 + sr, jmax - 1);
+  const bool scale = reg == 2 || reg == 4;
+  __shared__ double sD[KC];
   double(*fast)[TL + 2] = fout ? sA : sB;
   double(*slow)[TL + 2] = fout ? sB : sA;
+  double pa[QN], pb[QN], pd = 0.0;
+  auto fetch = [&](int kc0) {
+    const int kn = min(KC, kend - kc0);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) pa[q] = F[(int64_t)(kc0 + min(kq + KS * q, kn - 1)) * m + si_];
+    // a pivot per thread, in every region (a load only some threads or some
+    // regions make would leave the compiler waiting for the whole fetch
+    // before the products)
+    const int kd = kc0 + min(tid, kn - 1);
+    pd = F[(int64_t)kd * m + kd];
+    if (reg == 0) {
+#pragma unroll
+      for (int q = 0; q < QN; ++q)
+        pb[q] = W[(int64_t)(kc0 + min(kq + KS * q, kn - 1) - k0) * m + sj_];
+    } else if (scale) {
+#pragma unroll
+      for (int q = 0; q < QN; ++q) pb[q] = F[(int64_t)(kc0 + min(kq + KS * q, kn - 1)) * m + sj_];
+    } else {
+#pragma unroll
+      for (int q = 0; q < QN; ++q)
+        pb[q] = X[(int64_t)(kc0 + min(kq + KS * q, kn - 1)) * nc + sj_];
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
   for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
     const int kn = min(KC, kend - kc0);
-    if (kc0 > kbeg) __syncthreads();
+    if (kc0 > kbeg) __syncthreads();  // the previous chunk's products are done with LDS
 #pragma unroll
-    for (int h = 0; h < NPASS; ++h) {
-      double a[QH], b[QH];
-      int kk[QH];
-#pragma unroll
-      for (int q = 0; q < QH; ++q) {
-        kk[q] = kc0 + min(kq + KS * (q + QH * h), kn - 1);
-        a[q] = F[(int64_t)kk[q] * m + si_];
-      }
-      if (reg == 0) {
-#pragma unroll
-        for (int q = 0; q < QH; ++q) b[q] = W[(int64_t)(kk[q] - k0) * m + sj_];
-      } else if (reg == 2 || reg == 4) {
-        double dk[QH];
-#pragma unroll
-        for (int q = 0; q < QH; ++q) {
-          b[q] = F[(int64_t)kk[q] * m + sj_];
-          dk[q] = F[(int64_t)kk[q] * m + kk[q]];
-        }
-#pragma unroll
-        for (int q = 0; q < QH; ++q) b[q] *= dk[q];
-      } else {
-#pragma unroll
-        for (int q = 0; q < QH; ++q) b[q] = X[(int64_t)kk[q] * nc + sj_];
-      }
-#pragma unroll
-      for (int q = 0; q < QH; ++q) {
-        const int k = kq + KS * (q + QH * h);
-        sA[k][sr] = (k < kn && iok) ? a[q] : 0.0;
-        sB[k][sr] = (k < kn && jok) ? b[q] : 0.0;
-      }
+    for (int q = 0; q < QN; ++q) {
+      const int k = kq + KS * q;
+      sA[k][sr] = (k < kn && iok) ? pa[q] : 0.0;
+      sB[k][sr] = (k < kn && jok) ? pb[q] : 0.0;
     }
+    if (scale && tid < KC) sD[tid] = pd;
     __syncthreads();
+    if (kc0 + KC < kend) fetch(kc0 + KC);
     // the staged rows k >= kn are zero, so whole steps of 4 are taken
     for (int k = 0; k < kn; k += 4) {
       double av[NBK], bv[NBK];
+      const double dk = scale ? sD[k + ls] : 1.0;
 #pragma unroll
-      for (int sb = 0; sb < NBK; ++sb) av[sb] = -slow[k + ls][ws + 16 * sb + lf];
+      for (int sb = 0; sb < NBK; ++sb) av[sb] = -(slow[k + ls][ws + 16 * sb + lf] * dk);
 #pragma unroll
       for (int fb = 0; fb < NBK; ++fb) bv[fb] = fast[k + ls][wf + 16 * fb + lf];
 #pragma unroll
@@ -616,8 +624,9 @@ __device__ inline int64_t gf_tile_of(int64_t r0, int64_t n_tiles) {
   return r0 + b;
 }
 
-// Two workgroups per CU (their LDS stages fit together): one's loads overlap
-// the other's matrix work.
+// The next chunk's loads overlap the current chunk's matrix work inside the
+// workgroup (the 128-wide tiles hold their accumulators and the fetched
+// chunk in the full register file, one workgroup per CU).
 template <int TL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gf_update_mfma(
     const GfTile *tiles, int64_t n_tiles, const GfFront *fr, int k0, double *base) {
@@ -687,6 +696,8 @@ __global__ __launch_bounds__(256) void k_gf_emit(const GfFront *fr, const int32_
 
 }  // namespace
 
+constexpr int64_t kLevelBlocks = 16384;  // workgroups of the init, extend-add and emit launches
+
 template <typename TA, typename T>
 void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA *A, T *panels,
                        T *dinv) {
@@ -708,8 +719,14 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
       maxz = std::max<int64_t>(maxz, std::max<int64_t>((int64_t)g.m * g.nc,
                                                        (int64_t)(g.m - g.nc) * (g.m - g.nc)));
     }
-    const int64_t zx = std::max<int64_t>(1, std::min<int64_t>((maxz + 255) / 256, 512));
-    k_gf_init<<<grid2(zx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts);
+    // about kLevelBlocks workgroups per level whatever the number of fronts
+    // (the kernel strides over fronts and entries): one row of workgroups
+    // per front sized for the largest would launch millions of idle ones on
+    // the leaf levels and too few for a lone top front
+    const int64_t gy = std::min<int64_t>(nf, 65535);
+    const int64_t zx = std::max<int64_t>(
+        1, std::min<int64_t>((maxz + 255) / 256, kLevelBlocks / gy));
+    k_gf_init<<<grid2(zx, gy), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts);
     const int64_t a0 = P.a_ptr[L], na = P.a_ptr[L + 1] - a0;
     if (na > 0)
       k_gf_scatter<TA><<<grid1((na + 255) / 256), 256, 0, st>>>(na, d.a_csr + a0, d.a_off + a0, A,
@@ -718,8 +735,8 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
     for (int pass = P.ext_lvl_pass[L]; pass < p_end; ++pass) {
       const int64_t e0 = P.ext_pass[pass], ne = P.ext_pass[pass + 1] - e0;
       if (ne > 0)
-        k_gf_extend<<<grid1(ne), 256, 0, st>>>(d.ext + e0, ne, d.fr, d.parent, d.rel, d.rel_off,
-                                               d.fronts);
+        k_gf_extend<<<grid1(std::min<int64_t>(ne, kLevelBlocks)), 256, 0, st>>>(
+            d.ext + e0, ne, d.fr, d.parent, d.rel, d.rel_off, d.fronts);
     }
     for (int s = P.lvl_step_ptr[L]; s < P.lvl_step_ptr[L + 1]; ++s) {
       const int k0 = P.step_k0[s];
@@ -764,8 +781,9 @@ void launch_gpu_factor(hipStream_t st, const GfPlan &P, const GfDev &d, const TA
       maxt = std::max<int64_t>(maxt, (int64_t)((g.m + kEmitTile - 1) / kEmitTile) *
                                          ((g.nc + kEmitTile - 1) / kEmitTile));
     }
-    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(maxt, 1024));
-    k_gf_emit<T><<<grid2(gx, nf), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts, d.rows, panels,
+    const int64_t ey = std::min<int64_t>(nf, 65535);
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(maxt, kLevelBlocks / ey));
+    k_gf_emit<T><<<grid2(gx, ey), 256, 0, st>>>(d.fr, d.lvl_sn + f0, nf, d.fronts, d.rows, panels,
                                                 dinv);
   }
 }

@@ -224,6 +224,15 @@ int fe_export_pattern(fe_ctx *ctx, int32_t *row_ptr, int32_t *col_idx, int32_t *
  * (host [n_supernodes + 1] offsets into perm).  Either pointer may be NULL. */
 int fe_export_ordering(fe_ctx *ctx, int32_t *perm, int32_t *sn_ptr);
 
+/* Export the supernodal structure of the factor (Sec. 5.1, the regional
+ * problems of the level-scheduled solve): per supernode s (host
+ * [n_supernodes] each), n_rows[s] = rows of its panel (its own columns,
+ * sn_ptr[s+1] - sn_ptr[s] of fe_export_ordering, first, then the rows below
+ * them), and level[s] = its level in the assembly tree (0 = leaves; every
+ * supernode's level is above its children's; the triangular sweeps run one
+ * launch per level).  Either pointer may be NULL.  Host work only. */
+int fe_export_supernodes(fe_ctx *ctx, int32_t *n_rows, int32_t *level);
+
 /* Assemble A (CSR values, FP32 for FE_PREC_MIXED / FP64 for FE_PREC_FP64,
  * device [nnz]) and b (FP64 device [n_dofs]) at state (q, v) (device [n_dofs]
  * each):  A = (1 + h alpha) M + h (beta + h) K(q),

@@ -87,6 +87,7 @@ SIGNATURES = {
     "fe_bind": (C.c_int, [_P, C.c_int32, _P, C.c_int64, _P]),
     "fe_export_pattern": (C.c_int, [_P, _P, _P, _P]),
     "fe_export_ordering": (C.c_int, [_P, _P, _P]),
+    "fe_export_supernodes": (C.c_int, [_P, _P, _P]),
     "fe_assemble": (C.c_int, [_P, C.POINTER(fe_params), _P, _P, _P, _P, _P]),
     "fe_factor_async": (C.c_int, [_P, _P, C.c_int64, _P]),
     "fe_factor_status": (C.c_int, [_P, C.POINTER(C.c_int64)]),

@@ -19,8 +19,14 @@ struct SnDev {          // one supernode of the factor, as the GPU sees it
                         // a multiple of kPanelAlign)
 };
 
+// One tile of a triangular sweep with its supernode's fields copied in, so
+// that a workgroup's first load (the descriptor) is its only dependent one
+// before the index and panel loads.
 struct TileDev {
-  int32_t s, r0, c0, pad;
+  int64_t panel_off;    // the supernode's panel (entry offset)
+  int64_t rows_off;     // its rows (offset into the rows array)
+  int32_t nc, m, ld;    // own columns, panel rows, leading dimension
+  int32_t r0, c0, pad;  // the tile's first row and column
 };
 
 // Control block of one CG solve (device memory, read back by the host).
@@ -91,11 +97,11 @@ template <typename T>
 void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, double *z,
                      const uint8_t *dof_fixed, const PcgState *state);
 template <typename T>
-void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
                     int tile_cols);
 template <typename T>
-void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
                     const PcgState *state, int tile_rows);
 

@@ -466,12 +466,12 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
-    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_sn, c->d_rows, pan, w, y, s, S.fwd_cols);
+    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_cols);
   }
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
-    launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_sn, c->d_rows, pan, dinv, y, z, s,
+    launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_rows, pan, dinv, y, z, s,
                       S.bwd_rows);
   }
   if (c->rot_on) launch_rot_out<T>(st, n / 3, (const T *)c->d_rotQ, z, s);
@@ -1319,11 +1319,15 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
     sn[s] = SnDev{S.sn[s].nc, S.sn[s].m, S.sn[s].dev_off, S.sn[s].rows_off, S.sn[s].ld, 0};
   HIP_TRY(up(c->d_sn, sn.data(), sn.size() * sizeof(SnDev)));
   HIP_TRY(up(c->d_rows, S.rows.data(), S.rows.size() * 4));
+  auto tile_dev = [&](int32_t s, int32_t r0, int32_t c0) {
+    const Supernode &q = S.sn[s];
+    return TileDev{q.dev_off, q.rows_off, q.nc, q.m, q.ld, r0, c0, 0};
+  };
   std::vector<TileDev> ft(S.fwd_tiles.size()), bt(S.bwd_tiles.size());
   for (size_t i = 0; i < ft.size(); ++i)
-    ft[i] = TileDev{S.fwd_tiles[i].s, S.fwd_tiles[i].r0, S.fwd_tiles[i].c0, 0};
+    ft[i] = tile_dev(S.fwd_tiles[i].s, S.fwd_tiles[i].r0, S.fwd_tiles[i].c0);
   for (size_t i = 0; i < bt.size(); ++i)
-    bt[i] = TileDev{S.bwd_tiles[i].s, S.bwd_tiles[i].r0, S.bwd_tiles[i].c0, 0};
+    bt[i] = tile_dev(S.bwd_tiles[i].s, S.bwd_tiles[i].r0, S.bwd_tiles[i].c0);
   HIP_TRY(up(c->d_ftiles, ft.data(), ft.size() * sizeof(TileDev)));
   HIP_TRY(up(c->d_btiles, bt.data(), bt.size() * sizeof(TileDev)));
   HIP_TRY(up(c->d_mftiles, S.mfwd_tiles.data(), S.mfwd_tiles.size() * sizeof(MTile)));
@@ -1410,6 +1414,15 @@ int fe_export_ordering(fe_ctx *c, int32_t *perm, int32_t *sn_ptr) {
   if (!c) return FE_EINVAL;
   if (perm) memcpy(perm, c->S.perm.data(), c->S.perm.size() * 4);
   if (sn_ptr) memcpy(sn_ptr, c->S.sn_ptr.data(), c->S.sn_ptr.size() * 4);
+  return FE_OK;
+}
+
+int fe_export_supernodes(fe_ctx *c, int32_t *n_rows, int32_t *level) {
+  if (!c) return FE_EINVAL;
+  for (size_t s = 0; s < c->S.sn.size(); ++s) {
+    if (n_rows) n_rows[s] = c->S.sn[s].m;
+    if (level) level[s] = c->S.sn[s].level;
+  }
   return FE_OK;
 }
 

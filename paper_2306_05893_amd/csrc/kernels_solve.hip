@@ -277,14 +277,20 @@ constexpr int kBC = kBwdCols;  // backward tile: kBC columns x BR rows (BR: 256.
 // three memory latencies instead of one per group of columns.
 template <typename T, int TC>
 __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
-                                                 const SnDev *__restrict__ sn,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels, T *w, T *y,
                                                  const PcgState *s) {
-  if (s && s->done) return;
+  // the descriptor, the control word and the kernel arguments are loaded
+  // together, one latency before the index and panel loads (the empty asm
+  // takes the values the tile needs, so that the compiler does not sink
+  // their loads below the exit branch)
+  const TileDev d = tiles[blockIdx.x];
+  const int done = s ? s->done : 0;
+  asm volatile("" ::"s"(d.panel_off), "s"(d.rows_off), "s"(d.nc), "s"(d.m), "s"(rows),
+               "s"(panels));
+  if (done) return;
   __shared__ T s_in[TC];
-  const TileDev t = tiles[blockIdx.x];
-  const SnDev d = sn[t.s];
+  const TileDev &t = d;
   const int32_t *rw = rows + d.rows_off;
   const int c0 = t.c0, ncol = min(d.nc - c0, TC);
   const int tid = (int)threadIdx.x;
@@ -330,17 +336,19 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
 // gathered.  Rows above a column's diagonal (zeros of L11^{-1}) are not read.
 template <typename T, int BR>
 __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
-                                                 const SnDev *__restrict__ sn,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels,
                                                  const T *__restrict__ dinv,
                                                  const T *__restrict__ y, double *z,
                                                  const PcgState *s) {
-  if (s && s->done) return;
+  const TileDev d = tiles[blockIdx.x];  // loaded with the control word, as in k_tri_fwd
+  const int done = s ? s->done : 0;
+  asm volatile("" ::"s"(d.panel_off), "s"(d.rows_off), "s"(d.nc), "s"(d.m), "s"(rows),
+               "s"(panels));
+  if (done) return;
   constexpr int NI = BR / 64, CPW = kBC / 4;
   __shared__ T s_v[BR];
-  const TileDev t = tiles[blockIdx.x];
-  const SnDev d = sn[t.s];
+  const TileDev &t = d;
   const int32_t *rw = rows + d.rows_off;
   const int r0 = t.r0, r1 = min(d.m, r0 + BR);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -504,32 +512,32 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
   k_tri_prep<T><<<cg_blocks(n), kBlock, 0, st>>>(n, r, w, y, z, fixed, state);
 }
 template <typename T>
-void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
                     int tile_cols) {
   if (n_tiles <= 0) return;
   switch (tile_cols) {
-    case 16: k_tri_fwd<T, 16><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
-    case 32: k_tri_fwd<T, 32><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
-    case 64: k_tri_fwd<T, 64><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
-    case 128: k_tri_fwd<T, 128><<<n_tiles, kFR, 0, st>>>(tiles, sn, rows, panels, w, y, state); break;
+    case 16: k_tri_fwd<T, 16><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
+    case 32: k_tri_fwd<T, 32><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
+    case 64: k_tri_fwd<T, 64><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
+    case 128: k_tri_fwd<T, 128><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
     default: throw std::runtime_error("forward tile width must be 16, 32, 64 or 128");
   }
 }
 template <typename T>
-void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnDev *sn,
+void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
                     const PcgState *state, int tile_rows) {
   if (n_tiles <= 0) return;
   switch (tile_rows) {
     case 256:
-      k_tri_bwd<T, 256><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      k_tri_bwd<T, 256><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
       break;
     case 512:
-      k_tri_bwd<T, 512><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      k_tri_bwd<T, 512><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
       break;
     case 1024:
-      k_tri_bwd<T, 1024><<<n_tiles, 256, 0, st>>>(tiles, sn, rows, panels, dinv, y, z, state);
+      k_tri_bwd<T, 1024><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
       break;
     default: throw std::runtime_error("backward tile height must be 256, 512 or 1024");
   }
@@ -547,9 +555,9 @@ void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles, const SnD
                                    const T *, double *);                                       \
   template void launch_tri_prep<T>(hipStream_t, int64_t, const double *, T *, T *, double *,   \
                                    const uint8_t *, const PcgState *);                         \
-  template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
+  template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, T *, T *, const PcgState *, int);\
-  template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int, const SnDev *,            \
+  template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, const T *, const T *, double *,  \
                                   const PcgState *, int);
 FE_INST(float)

@@ -197,6 +197,15 @@ class FEContext:
                                               snp.ctypes.data_as(C.c_void_p)))
         return perm, snp
 
+    def export_supernodes(self):
+        """Rows of each supernode's panel and its assembly-tree level."""
+        s = self.sizes
+        m = np.empty(s.n_supernodes, dtype=np.int32)
+        lev = np.empty(s.n_supernodes, dtype=np.int32)
+        self._chk(self.lib.fe_export_supernodes(self.h, m.ctypes.data_as(C.c_void_p),
+                                                lev.ctypes.data_as(C.c_void_p)))
+        return m, lev
+
     def host_factor_apply(self, A_host, r_host):
         """Host-only: factor FP64 CSR values and apply P^{-1} to rows of r."""
         A = np.ascontiguousarray(A_host, dtype=np.float64)

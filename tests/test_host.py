@@ -119,6 +119,47 @@ def test_ordering_is_a_permutation(mesh):
     assert ctx.sizes.factor_lower <= ctx.sizes.factor_entries
 
 
+@pytest.mark.parametrize("mesh", ["tiny_tet", "tiny_hex", "hex_diff"])
+def test_supernodes_cover_the_symbolic_factor(mesh):
+    """Panel rows and levels against the structure of the Cholesky factor of
+    the permuted free block, found by boolean elimination: every supernode's
+    panel holds at least the rows its columns reach, the lower entries sum to
+    the reported count, and each column's parent in the elimination tree lies
+    in the same supernode or one at a higher level."""
+    w = synth.make(mesh)
+    ctx = _ctx(w)
+    perm, snp = ctx.export_ordering()
+    m, lev = ctx.export_supernodes()
+    rp, ci, _ = ctx.export_pattern()
+    nf = int(snp[-1])
+    inv = np.full(w.n_dofs, -1)
+    inv[perm[:nf]] = np.arange(nf)
+    S = np.zeros((nf, nf), dtype=bool)
+    for r in range(w.n_dofs):
+        for c in ci[rp[r]:rp[r + 1]]:
+            if inv[r] >= 0 and inv[c] >= 0:
+                S[inv[r], inv[c]] = S[inv[c], inv[r]] = True
+    S = np.tril(S)
+    parent = np.full(nf, -1)
+    for j in range(nf):
+        rows = np.nonzero(S[j + 1:, j])[0] + j + 1
+        if rows.size:
+            parent[j] = rows[0]
+            S[np.ix_(rows, rows)] |= np.tril(np.ones((rows.size, rows.size), dtype=bool))
+    sn_of = np.repeat(np.arange(len(m)), np.diff(snp))
+    nc = np.diff(snp)
+    for s in range(len(m)):
+        a, b = snp[s], snp[s + 1]
+        reach = np.count_nonzero(S[a:, a:b].any(axis=1))
+        assert nc[s] <= reach <= m[s] <= nf - a
+    lower = int((m.astype(np.int64) * nc - nc * (nc - 1) // 2).sum())
+    assert lower == ctx.sizes.factor_lower
+    assert lev.min() == 0 and lev.max() == ctx.sizes.n_levels - 1
+    for j in range(nf):
+        if parent[j] >= 0 and sn_of[parent[j]] != sn_of[j]:
+            assert lev[sn_of[parent[j]]] > lev[sn_of[j]]
+
+
 @pytest.mark.parametrize("mesh,leaf", [("tiny_tet", 4), ("tiny_hex", 6), ("tet_beam", 0),
                                        ("tet_beam", 8)])
 def test_host_factor_applies_inverse(mesh, leaf):

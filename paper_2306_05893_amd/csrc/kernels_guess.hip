@@ -24,11 +24,13 @@ __device__ inline double wave_sum(double v) {
 constexpr int kHistDots = kHist * (kHist + 1) / 2 + kHist;  // G (upper) and V^T b
 constexpr int kHistBlocks = 256;
 
-// W = A V for the m history vectors: G lanes per row as in k_spmv; each entry
-// of the row is used with the m interleaved values of its column (one 64-byte
-// row of V), the row sums reduced over the G lanes, lane sub writes column sub.
+// W = A V for every slot of the ring (the m newest vectors may sit in any
+// of them): G lanes per row as in k_spmv; each entry of the row is used with
+// the kHist interleaved values of its column (one row of V), the row sums
+// reduced over the G lanes, lane sub writes column sub.  Slots never filled
+// give columns that the solve does not read.
 template <typename T, int G>
-__global__ __launch_bounds__(kBlock) void k_hist_spmv(int64_t n, int m,
+__global__ __launch_bounds__(kBlock) void k_hist_spmv(int64_t n,
                                                       const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const T *__restrict__ val,
@@ -59,52 +61,70 @@ __global__ __launch_bounds__(kBlock) void k_hist_spmv(int64_t n, int m,
   double mine = acc[0];
 #pragma unroll
   for (int j = 1; j < kHist; ++j) mine = sub == j ? acc[j] : mine;
-  if (row < n) W[row * kHist + sub] = sub < m ? mine : 0.0;
+  if (row < n) W[row * kHist + sub] = mine;
 }
 
 // Per-block partials of G_ij = V_i . W_j (i <= j) and r_i = V_i . b, stored
-// value-major: part[q * kHistBlocks + block].
+// value-major: part[q * kHistBlocks + block].  blockIdx.y takes rows
+// [kHistRG y, kHistRG (y + 1)) of G (all kHist columns are accumulated, the
+// ones below the diagonal are not written), so that a thread holds
+// kHistRG (kHist + 1) sums.
+constexpr int kHistRG = 4;
+constexpr int kHistAcc = kHistRG * (kHist + 1);
+static_assert(kHist % kHistRG == 0, "whole row groups");
+
+__device__ inline int hist_gidx(int i, int j) {  // upper-triangle index of (i, j), i <= j
+  return i * kHist - i * (i - 1) / 2 + (j - i);
+}
+
 __global__ __launch_bounds__(kBlock) void k_hist_dots(int64_t n, const double *__restrict__ V,
                                                       const double *__restrict__ W,
                                                       const double *__restrict__ b,
                                                       double *part) {
-  __shared__ double s_red[kBlock / 64][kHistDots];
-  double acc[kHistDots];
+  __shared__ double s_red[kBlock / 64][kHistAcc];
+  const int i0 = blockIdx.y * kHistRG;
+  double acc[kHistAcc];
 #pragma unroll
-  for (int q = 0; q < kHistDots; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kHistAcc; ++q) acc[q] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kBlock;
   for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) {
-    double v[kHist], w[kHist];
-    const double2 *vr = reinterpret_cast<const double2 *>(V + k * kHist);
+    double v[kHistRG], w[kHist];
+    const double2 *vr = reinterpret_cast<const double2 *>(V + k * kHist + i0);
     const double2 *wr = reinterpret_cast<const double2 *>(W + k * kHist);
 #pragma unroll
-    for (int j = 0; j < kHist / 2; ++j) {
-      const double2 a = vr[j], c = wr[j];
+    for (int j = 0; j < kHistRG / 2; ++j) {
+      const double2 a = vr[j];
       v[2 * j] = a.x;
       v[2 * j + 1] = a.y;
+    }
+#pragma unroll
+    for (int j = 0; j < kHist / 2; ++j) {
+      const double2 c = wr[j];
       w[2 * j] = c.x;
       w[2 * j + 1] = c.y;
     }
     const double bk = b[k];
-    int q = 0;
 #pragma unroll
-    for (int i = 0; i < kHist; ++i)
+    for (int r = 0; r < kHistRG; ++r) {
 #pragma unroll
-      for (int j = i; j < kHist; ++j) acc[q++] += v[i] * w[j];
-#pragma unroll
-    for (int i = 0; i < kHist; ++i) acc[q++] += v[i] * bk;
+      for (int j = 0; j < kHist; ++j) acc[r * (kHist + 1) + j] += v[r] * w[j];
+      acc[r * (kHist + 1) + kHist] += v[r] * bk;
+    }
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < kHistDots; ++q) {
+  for (int q = 0; q < kHistAcc; ++q) {
     const double t = wave_sum(acc[q]);
     if (lane == 0) s_red[wv][q] = t;
   }
   __syncthreads();
-  if (threadIdx.x < kHistDots) {
+  if (threadIdx.x < kHistAcc) {
+    const int r = threadIdx.x / (kHist + 1), j = threadIdx.x % (kHist + 1), i = i0 + r;
     double t = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) t += s_red[i][threadIdx.x];
-    part[threadIdx.x * kHistBlocks + blockIdx.x] = t;
+    for (int u = 0; u < kBlock / 64; ++u) t += s_red[u][threadIdx.x];
+    // column kHist holds V_i . b, stored after the upper triangle of G
+    const int q = j == kHist ? kHist * (kHist + 1) / 2 + i : (j >= i ? hist_gidx(i, j) : -1);
+    if (q >= 0) part[q * kHistBlocks + blockIdx.x] = t;
   }
 }
 
@@ -122,16 +142,15 @@ __global__ __launch_bounds__(kBlock) void k_hist_solve(int m, int newest, const 
     t = wave_sum(t);
     if (lane == 0) s_val[q] = t;
   }
+  // the factor and the triangular solves in LDS (one thread works on them)
+  __shared__ double L[kHist][kHist];
+  __shared__ double y[kHist], c[kHist];
+  __shared__ int ord[kHist];
+  __shared__ bool keep[kHist];
   __syncthreads();
   if (threadIdx.x != 0) return;
   constexpr double kHistDrop = 1e-13;
-  auto gidx = [](int i, int j) {  // upper-triangle index of (min, max)
-    const int a = i < j ? i : j, b = i < j ? j : i;
-    return a * kHist - a * (a - 1) / 2 + (b - a);
-  };
-  int ord[kHist];
-  bool keep[kHist];
-  double L[kHist][kHist], y[kHist], c[kHist];
+  auto gidx = [](int i, int j) { return i < j ? hist_gidx(i, j) : hist_gidx(j, i); };
   for (int t = 0; t < m; ++t) ord[t] = (newest - t + kHist) % kHist;
   for (int t = 0; t < m; ++t) {
     const int i = ord[t];
@@ -168,19 +187,18 @@ __global__ __launch_bounds__(kBlock) void k_hist_solve(int m, int newest, const 
   for (int t = 0; t < m; ++t) coef[ord[t]] = c[t];
 }
 
-// x = V coef
+// x = V coef over the slots with a coefficient (the others may never have
+// been filled: their contents are not read)
 __global__ __launch_bounds__(kBlock) void k_hist_combine(int64_t n, const double *__restrict__ V,
                                                          const double *__restrict__ coef,
                                                          double *__restrict__ x) {
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (k >= n) return;
-  const double2 *vr = reinterpret_cast<const double2 *>(V + k * kHist);
+  const double *vr = V + k * kHist;
   double s = 0.0;
 #pragma unroll
-  for (int j = 0; j < kHist / 2; ++j) {
-    const double2 a = vr[j];
-    s += coef[2 * j] * a.x + coef[2 * j + 1] * a.y;
-  }
+  for (int j = 0; j < kHist; ++j)
+    if (coef[j] != 0.0) s += coef[j] * vr[j];
   x[k] = s;
 }
 
@@ -198,8 +216,8 @@ void launch_hist_guess(hipStream_t st, int64_t n, int m, int newest, const int32
                        const int32_t *col, const T *val, const double *V, double *W,
                        const double *b, double *part, double *coef, double *x) {
   const unsigned rb = (unsigned)((n * kHist + kBlock - 1) / kBlock);
-  k_hist_spmv<T, kHist><<<rb, kBlock, 0, st>>>(n, m, row_ptr, col, val, V, W);
-  k_hist_dots<<<kHistBlocks, kBlock, 0, st>>>(n, V, W, b, part);
+  k_hist_spmv<T, kHist><<<rb, kBlock, 0, st>>>(n, row_ptr, col, val, V, W);
+  k_hist_dots<<<dim3(kHistBlocks, kHist / kHistRG), kBlock, 0, st>>>(n, V, W, b, part);
   k_hist_solve<<<1, kBlock, 0, st>>>(m, newest, part, kHistBlocks, coef);
   k_hist_combine<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, st>>>(n, V, coef, x);
 }

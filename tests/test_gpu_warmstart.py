@@ -45,9 +45,10 @@ def test_trajectory_with_initial_guess(prec, warm):
     assert sum(its[warm][2:]) <= sum(its[0][2:])
 
 
+@pytest.mark.parametrize("prior", [3, 19])
 @pytest.mark.parametrize("warm", [1, 4])
 @pytest.mark.parametrize("prec", [FE_PREC_FP64, FE_PREC_MIXED])
-def test_repeated_step_starts_at_its_solution(prec, warm):
+def test_repeated_step_starts_at_its_solution(prec, warm, prior):
     # The same step taken twice from the same state: A and b are the same
     # bit for bit (the assembly sums in a fixed order) and the first
     # solution a1 met the recomputed-residual test.  warm_start = 1 starts
@@ -55,18 +56,44 @@ def test_repeated_step_starts_at_its_solution(prec, warm):
     # The projection (m = 4) starts at the A-norm best approximation in a
     # span that contains a1, whose residual is within sqrt(cond A) of a1's;
     # a fresh factor every step then finishes in at most 2 iterations.
+    # After 19 prior steps the 8-slot ring of earlier solutions has wrapped,
+    # so the m = 4 newest ones sit in any of its slots.
     w = synth.make("hex_diff")
     sim = Simulation(w, prec=prec, factor_on_gpu=True)
     opts = StepOptions(rel_tol=1e-8, max_it=500, refresh=1, lag=0, warm_start=warm)
-    for _ in range(3):
+    for _ in range(prior):
         sim.step(opts)
     q, v = sim.q.clone(), sim.v.clone()
     st1 = sim.step(opts)
     sim.q.copy_(q)
     sim.v.copy_(v)
     st2 = sim.step(opts)
-    print(f"[warm] repeated step prec={prec} warm_start={warm}: iterations "
+    print(f"[warm] repeated step prec={prec} warm_start={warm} after {prior}: iterations "
           f"{st1.solve.iterations} then {st2.solve.iterations} (rel-res {st2.solve.rel_res:.1e})")
     assert st1.solve.iterations >= 1 and st2.solve.rel_res <= 1e-8
     assert st2.solve.iterations == 0 if warm == 1 else st2.solve.iterations <= 2
+    sim.ctx.close()
+
+
+@pytest.mark.parametrize("prec", [FE_PREC_FP64, FE_PREC_MIXED])
+def test_projection_uses_the_newest_solutions_after_the_ring_wraps(prec):
+    # m = 4 of the 8 slots, 19 earlier steps: the newest solutions sit in
+    # any slot.  The factor of step 0 stays in use, so a guess without the
+    # previous solution costs the stale factor several iterations; the
+    # projection onto a span holding that solution is independent of the
+    # factor and, as with a fresh factor, passes the residual test at once.
+    w = synth.make("hex_diff")
+    sim = Simulation(w, prec=prec, factor_on_gpu=True)
+    opts = StepOptions(rel_tol=1e-8, max_it=500, refresh=1000, lag=0, warm_start=4)
+    for _ in range(19):
+        sim.step(opts)
+    q, v = sim.q.clone(), sim.v.clone()
+    st1 = sim.step(opts)
+    sim.q.copy_(q)
+    sim.v.copy_(v)
+    st2 = sim.step(opts)
+    print(f"[warm] wrapped ring prec={prec}: iterations {st1.solve.iterations} then "
+          f"{st2.solve.iterations} (rel-res {st2.solve.rel_res:.1e})")
+    assert st1.solve.iterations >= 3
+    assert st2.solve.iterations <= 2 and st2.solve.rel_res <= 1e-8
     sim.ctx.close()

@@ -188,12 +188,14 @@ void launch_hist_push(hipStream_t st, int64_t n, int slot, const double *x, doub
 int64_t hist_part_doubles();
 
 // Rotation of the stale preconditioner: per-node rotations R_n of state q
-// (S: 9 FP64 accumulators per node, zero on entry and cleared again), the
-// identity, Q_n = R_n(t) R_n(t0)^T, and the sweep input w = Q^T r / output
-// z = Q z per node.
+// (Fe: 9 FP64 per element, the element-centre deformation gradients; ne_ptr
+// / ne_idx: the elements of each node, ascending), the identity,
+// Q_n = R_n(t) R_n(t0)^T, and the sweep input w = Q^T r / output z = Q z per
+// node.
 void launch_node_rotations(hipStream_t st, int elem_type, int64_t n_elems, const int32_t *conn,
                            const double *X, const double *q, int64_t n_nodes,
-                           const uint8_t *dof_fixed, double *S, double *Rn);
+                           const uint8_t *dof_fixed, const int32_t *ne_ptr,
+                           const int32_t *ne_idx, double *Fe, double *Rn);
 void launch_rot_identity(hipStream_t st, int64_t n_nodes, double *R);
 template <typename T>
 void launch_rot_q(hipStream_t st, int64_t n_nodes, const double *Rt, const double *R0, T *Q);

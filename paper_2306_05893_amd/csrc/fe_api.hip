@@ -160,7 +160,8 @@ struct fe_ctx {
   // rotation of the stale factor: node accumulators, rotations of the
   // current state, of the state of each factor job (two, alternating) and of
   // the factor in each slot; Q = R_now R_slot^T in the context precision
-  double *d_rotS = nullptr, *d_Rnow = nullptr, *d_Rjob[2] = {nullptr, nullptr},
+  int32_t *d_ne_ptr = nullptr, *d_ne_idx = nullptr;  // elements of each node (rotations)
+  double *d_rotFe = nullptr, *d_Rnow = nullptr, *d_Rjob[2] = {nullptr, nullptr},
          *d_Rslot[2] = {nullptr, nullptr};
   void *d_rotQ = nullptr;
   bool rot_valid = false;  // d_Rnow holds the rotations of this step's state
@@ -230,8 +231,8 @@ enum {
   L_MU, L_KMU, L_MMU, L_TMV, L_W, L_Y, L_A, L_PART1, L_PART2, L_STATE, L_GF_FRONTS, L_GF_FR,
   L_GF_LVLSN, L_GF_ACSR, L_GF_AOFF, L_GF_PARENT, L_GF_REL, L_GF_RELOFF, L_GF_EXT, L_GF_PANELSN,
   L_GF_UPD, L_GF_ASNAP, L_GF_STATUS, L_BLKPTR, L_BLKPOS, L_BLKNODE, L_BLKSRC, L_EBUF, L_RBUF,
-  L_MFT, L_MBT, L_HERR, L_MBDOF, L_HISTV, L_HISTW, L_HISTP, L_ROTS, L_RNOW, L_RJOB0, L_RJOB1,
-  L_RSLOT0, L_RSLOT1, L_ROTQ
+  L_MFT, L_MBT, L_HERR, L_MBDOF, L_HISTV, L_HISTW, L_HISTP, L_NEPTR, L_NEIDX, L_ROTFE, L_RNOW,
+  L_RJOB0, L_RJOB1, L_RSLOT0, L_RSLOT1, L_ROTQ
 };
 
 Layout make_layout(const fe_ctx *c, int prec) {
@@ -297,7 +298,10 @@ Layout make_layout(const fe_ctx *c, int prec) {
   L.add(n * kHist * 8);  // A times them
   L.add(hist_part_doubles() * 8);
   const int64_t nn = n / 3;
-  for (int i = 0; i < 6; ++i) L.add(nn * 9 * 8);  // S, R_now, R_job x2, R_slot x2
+  L.add((nn + 1) * 4);                             // elements of each node: offsets,
+  L.add((int64_t)P.n_elems * P.nen * 4);           //   element indices
+  L.add((int64_t)P.n_elems * 9 * 8);               // element-centre deformation gradients
+  for (int i = 0; i < 5; ++i) L.add(nn * 9 * 8);  // R_now, R_job x2, R_slot x2
   L.add(nn * 9 * ts);                              // Q
   return L;
 }
@@ -912,7 +916,7 @@ int step_impl(fe_ctx *c, double *q, double *v, const fe_params *p, const fe_step
   c->rot_valid = o->rotate_precond != 0;
   if (c->rot_valid)
     launch_node_rotations(st, c->elem_type, c->P.n_elems, c->d_conn, c->d_X, q, n / 3,
-                          c->d_dof_fixed, c->d_rotS, c->d_Rnow);
+                          c->d_dof_fixed, c->d_ne_ptr, c->d_ne_idx, c->d_rotFe, c->d_Rnow);
   const int R = o->refresh, d = o->lag;
   if (R > 0 && step % R == 0) {
     bool busy;
@@ -1005,7 +1009,7 @@ int adjoint_impl(fe_ctx *c, const double *q_n, const double *v_n, const double *
   c->rot_valid = o && o->rotate_precond;
   if (c->rot_valid)
     launch_node_rotations(st, c->elem_type, c->P.n_elems, c->d_conn, c->d_X, q_n, n / 3,
-                          c->d_dof_fixed, c->d_rotS, c->d_Rnow);
+                          c->d_dof_fixed, c->d_ne_ptr, c->d_ne_idx, c->d_rotFe, c->d_Rnow);
   if (o && o->refresh > 0 && c->active_slot < 0) {
     // no factor yet: factor this A synchronously
     const int64_t tag = (int64_t(1) << 40) + c->step_count;
@@ -1263,7 +1267,9 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_histV = ptr_at<double>(w, L, L_HISTV);
   c->d_histW = ptr_at<double>(w, L, L_HISTW);
   c->d_histP = ptr_at<double>(w, L, L_HISTP);
-  c->d_rotS = ptr_at<double>(w, L, L_ROTS);
+  c->d_ne_ptr = ptr_at<int32_t>(w, L, L_NEPTR);
+  c->d_ne_idx = ptr_at<int32_t>(w, L, L_NEIDX);
+  c->d_rotFe = ptr_at<double>(w, L, L_ROTFE);
   c->d_Rnow = ptr_at<double>(w, L, L_RNOW);
   c->d_Rjob[0] = ptr_at<double>(w, L, L_RJOB0);
   c->d_Rjob[1] = ptr_at<double>(w, L, L_RJOB1);
@@ -1335,9 +1341,17 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   HIP_TRY(up(c->d_mbdofs, S.mbwd_dofs.data(), S.mbwd_dofs.size() * 4));
   HIP_TRY(up(c->d_state, c->h_state, sizeof(PcgState)));
   {
-    // rotation accumulators zero, rotations of jobs and slots the identity
+    // the elements of each node in ascending order (the rotation's sums run
+    // in that fixed order); rotations of jobs and slots the identity
     const int64_t nn = P.n / 3;
-    launch_zero(st, 9 * nn, c->d_rotS);
+    std::vector<int32_t> ne_ptr(nn + 1, 0), ne_idx((size_t)P.n_elems * P.nen);
+    for (size_t k = 0; k < ne_idx.size(); ++k) ++ne_ptr[P.conn[k] + 1];
+    for (int64_t i = 0; i < nn; ++i) ne_ptr[i + 1] += ne_ptr[i];
+    std::vector<int32_t> fill(ne_ptr.begin(), ne_ptr.end() - 1);
+    for (int64_t e = 0; e < P.n_elems; ++e)
+      for (int a = 0; a < P.nen; ++a) ne_idx[fill[P.conn[e * P.nen + a]]++] = (int32_t)e;
+    HIP_TRY(up(c->d_ne_ptr, ne_ptr.data(), ne_ptr.size() * 4));
+    HIP_TRY(up(c->d_ne_idx, ne_idx.data(), ne_idx.size() * 4));
     for (double *R : {c->d_Rnow, c->d_Rjob[0], c->d_Rjob[1], c->d_Rslot[0], c->d_Rslot[1]})
       launch_rot_identity(st, nn, R);
     HIP_TRY(hipGetLastError());

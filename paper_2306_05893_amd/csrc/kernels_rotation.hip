@@ -43,13 +43,13 @@ __device__ inline void inv_t3(const double *M, double d, double *R) {
 }
 
 // Deformation gradient at the element centre, F = sum_a x_a (x) g_a with g_a
-// the rest-configuration gradient of N_a there, added into the element's
-// nodes (S[node] += F, 9 FP64 atomics per node).
+// the rest-configuration gradient of N_a there, one element per thread,
+// stored per element (Fe[9 e .. 9 e + 9), row-major).
 template <int NEN>
-__global__ __launch_bounds__(kBlock) void k_rot_accum(int64_t n_elems,
-                                                      const int32_t *__restrict__ conn,
-                                                      const double *__restrict__ X,
-                                                      const double *__restrict__ q, double *S) {
+__global__ __launch_bounds__(kBlock) void k_rot_elem(int64_t n_elems,
+                                                     const int32_t *__restrict__ conn,
+                                                     const double *__restrict__ X,
+                                                     const double *__restrict__ q, double *Fe) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n_elems) return;
   int nd[NEN];
@@ -88,36 +88,35 @@ __global__ __launch_bounds__(kBlock) void k_rot_accum(int64_t n_elems,
   }
   double Jit[9];
   inv_t3(J, det3d(J), Jit);  // J^{-T}
-  double F[9];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      F[i * 3 + j] = Fx[i * 3] * Jit[j * 3] + Fx[i * 3 + 1] * Jit[j * 3 + 1] +
-                     Fx[i * 3 + 2] * Jit[j * 3 + 2];  // (Fx J^{-1})_{ij}
-#pragma unroll
-  for (int a = 0; a < NEN; ++a) {
-    double *s = S + 9 * (int64_t)nd[a];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) atomicAdd(s + k, F[k]);
-  }
+      Fe[9 * e + i * 3 + j] = Fx[i * 3] * Jit[j * 3] + Fx[i * 3 + 1] * Jit[j * 3 + 1] +
+                              Fx[i * 3 + 2] * Jit[j * 3 + 2];  // (Fx J^{-1})_{ij}
 }
 
-// R_n = rotation factor of the polar decomposition of S_n (Newton iteration
-// R <- (R + R^{-T}) / 2); the identity for nodes with a fixed DOF and for
-// nodes whose S_n is singular or inverted.  Clears S_n for the next pass.
-__global__ __launch_bounds__(kBlock) void k_rot_node(int64_t n_nodes, double *S,
+// R_n = rotation factor of the polar decomposition of S_n, the sum of the
+// centre deformation gradients of the elements around node n (in ascending
+// element order, ne_idx[ne_ptr[n] .. ne_ptr[n + 1])), by the Newton
+// iteration R <- (R + R^{-T}) / 2; the identity for nodes with a fixed DOF
+// and for nodes whose S_n is singular or inverted.
+__global__ __launch_bounds__(kBlock) void k_rot_node(int64_t n_nodes,
+                                                     const int32_t *__restrict__ ne_ptr,
+                                                     const int32_t *__restrict__ ne_idx,
+                                                     const double *__restrict__ Fe,
                                                      const uint8_t *__restrict__ dof_fixed,
                                                      double *Rn) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n_nodes) return;
-  double R[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    R[k] = S[9 * i + k];
-    S[9 * i + k] = 0.0;
-  }
   bool ok = !(dof_fixed[3 * i] | dof_fixed[3 * i + 1] | dof_fixed[3 * i + 2]);
+  double R[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (ok)
+    for (int32_t k = ne_ptr[i]; k < ne_ptr[i + 1]; ++k) {
+      const double *f = Fe + 9 * (int64_t)ne_idx[k];
+#pragma unroll
+      for (int u = 0; u < 9; ++u) R[u] += f[u];
+    }
   for (int it = 0; ok && it < 40; ++it) {
     const double d = det3d(R);
     if (!(d > 0.0)) {
@@ -195,14 +194,16 @@ unsigned grid_of(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 void launch_node_rotations(hipStream_t st, int elem_type, int64_t n_elems, const int32_t *conn,
                            const double *X, const double *q, int64_t n_nodes,
-                           const uint8_t *dof_fixed, double *S, double *Rn) {
+                           const uint8_t *dof_fixed, const int32_t *ne_ptr,
+                           const int32_t *ne_idx, double *Fe, double *Rn) {
   if (n_elems > 0) {
     if (elem_type == 8)
-      k_rot_accum<8><<<grid_of(n_elems), kBlock, 0, st>>>(n_elems, conn, X, q, S);
+      k_rot_elem<8><<<grid_of(n_elems), kBlock, 0, st>>>(n_elems, conn, X, q, Fe);
     else
-      k_rot_accum<4><<<grid_of(n_elems), kBlock, 0, st>>>(n_elems, conn, X, q, S);
+      k_rot_elem<4><<<grid_of(n_elems), kBlock, 0, st>>>(n_elems, conn, X, q, Fe);
   }
-  if (n_nodes > 0) k_rot_node<<<grid_of(n_nodes), kBlock, 0, st>>>(n_nodes, S, dof_fixed, Rn);
+  if (n_nodes > 0)
+    k_rot_node<<<grid_of(n_nodes), kBlock, 0, st>>>(n_nodes, ne_ptr, ne_idx, Fe, dof_fixed, Rn);
 }
 
 void launch_rot_identity(hipStream_t st, int64_t n_nodes, double *R) {

@@ -109,8 +109,11 @@ def _leg(r):
             "factor_lag_mean": round(r["factor_lag_mean"], 1)}
 
 
-# kernel names as rocprofv3 reports them (default tile extents 64 / 512)
-KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd<float, 64>", "trisolve_bwd": "k_tri_bwd<float, 512>",
+# kernel names as rocprofv3 reports them (default tile extents 64 / 512; the
+# sweeps of the hex block and the hex beam read their panels non-temporally,
+# both factors being larger than the last-level cache)
+KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd<float, 64, true>",
+                 "trisolve_bwd": "k_tri_bwd<float, 512, true>",
                  "spmv": "k_spmv<float, 16>", "element": "k_elem_hex<float, 1, true>"}
 
 

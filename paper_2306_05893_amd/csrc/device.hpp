@@ -92,18 +92,20 @@ void launch_spmv(hipStream_t st, int64_t n, int rows_per_lanes, const int32_t *r
                  const double *w, double *dot_partial, int *n_partial, const PcgState *state);
 int spmv_lanes_for(double avg_row_nnz);
 
-// Triangular sweeps z = P^{-1} r with P = L D L^T in explicit-inverse panels.
+// Triangular sweeps z = P^{-1} r with P = L D L^T in explicit-inverse panels
+// (stream: read the panels non-temporally, for a factor larger than the
+// last-level cache).
 template <typename T>
 void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, double *z,
                      const uint8_t *dof_fixed, const PcgState *state);
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
-                    int tile_cols);
+                    int tile_cols, bool stream);
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state, int tile_rows);
+                    const PcgState *state, int tile_rows, bool stream);
 
 // Many right-hand sides: DOF-major n x ld blocks (ld = k rounded up to the
 // tile width bn, 64 or 128), w/y in the factor's precision, z FP64.

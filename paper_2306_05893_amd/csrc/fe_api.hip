@@ -195,6 +195,10 @@ struct fe_ctx {
   int64_t t_count[kTimedKinds] = {};
   int *h_flag = nullptr;  // pinned host word for error flags read back
   std::vector<double> fwd_level_bytes, bwd_level_bytes;
+  // the sweeps read the panels non-temporally when one factor slot exceeds
+  // the 256 MB last-level cache (a smaller factor stays cached between
+  // applications)
+  bool panel_stream = false;
 
   int fail(int code, const char *fmt, ...) {
     char buf[1024];
@@ -470,13 +474,14 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
-    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_cols);
+    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_cols,
+                      c->panel_stream);
   }
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
     launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_rows, pan, dinv, y, z, s,
-                      S.bwd_rows);
+                      S.bwd_rows, c->panel_stream);
   }
   if (c->rot_on) launch_rot_out<T>(st, n / 3, (const T *)c->d_rotQ, z, s);
 }
@@ -1237,6 +1242,7 @@ int fe_bind(fe_ctx *c, int32_t prec, void *d_ws, int64_t ws_bytes, void *stream)
   c->d_rows = ptr_at<int32_t>(w, L, L_ROWS);
   c->d_ftiles = ptr_at<TileDev>(w, L, L_FT);
   c->d_btiles = ptr_at<TileDev>(w, L, L_BT);
+  c->panel_stream = c->S.dev_panel_entries * c->tsize > ((int64_t)256 << 20);
   c->d_panels[0] = w + L.off[L_PAN0];
   c->d_panels[1] = w + L.off[L_PAN1];
   c->d_dinv[0] = w + L.off[L_DINV0];

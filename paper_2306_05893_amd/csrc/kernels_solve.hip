@@ -274,12 +274,21 @@ constexpr int kBC = kBwdCols;  // backward tile: kBC columns x BR rows (BR: 256.
 // subtract from w.  Entries above the diagonal of L11^{-1} are skipped.
 // All TC panel loads of a row are issued before the gather of the inputs
 // w[rows[j]] (an index load and a dependent load), so one tile costs about
-// three memory latencies instead of one per group of columns.  The panels
-// are read non-temporally (each entry once per application, 11.6 GB on the
-// largest mesh): the stream then does not evict the vectors, row indices
-// and descriptors that the gathers and atomics reuse (forward 151.6 ->
-// 138.9 us, backward 155.1 -> 148.6 us per launch on the 1.39 M-DOF block).
-template <typename T, int TC>
+// three memory latencies instead of one per group of columns.  With NT the
+// panels are read non-temporally, for factors larger than the last-level
+// cache (each entry is read once per application, 11.6 GB on the largest
+// mesh): the stream then does not evict the vectors, row indices and
+// descriptors that the gathers and atomics reuse (forward 151.6 -> 138.9 us,
+// backward 155.1 -> 148.6 us per launch on the 1.39 M-DOF block).  A factor
+// that fits in that cache is read with ordinary loads and stays there from
+// one application to the next.
+template <bool NT, typename T>
+__device__ inline T panel_load(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <typename T, int TC, bool NT>
 __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels, T *w, T *y,
@@ -312,10 +321,10 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
   T g[TC];
   if (full) {
 #pragma unroll
-    for (int j = 0; j < TC; ++j) g[j] = __builtin_nontemporal_load(G + j * m);
+    for (int j = 0; j < TC; ++j) g[j] = panel_load<NT>(G + j * m);
   } else {
 #pragma unroll
-    for (int j = 0; j < TC; ++j) g[j] = j < lim ? __builtin_nontemporal_load(G + j * m) : T(0);
+    for (int j = 0; j < TC; ++j) g[j] = j < lim ? panel_load<NT>(G + j * m) : T(0);
   }
   if (tid < TC) s_in[tid] = tid < ncol ? w[din] : T(0);
   __syncthreads();
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
 // Each wavefront handles CPW consecutive columns (lanes stride over rows)
 // and issues all BR/64 x CPW of its panel loads before the inputs v are
 // gathered.  Rows above a column's diagonal (zeros of L11^{-1}) are not read.
-template <typename T, int BR>
+template <typename T, int BR, bool NT>
 __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels,
@@ -373,7 +382,7 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
     for (int q = 0; q < NI; ++q) {
       const int i = r0 + lane + 64 * q;
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) g[q][c] = __builtin_nontemporal_load(G + c * m + i);
+      for (int c = 0; c < CPW; ++c) g[q][c] = panel_load<NT>(G + c * m + i);
     }
   } else {
 #pragma unroll
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
       const bool ok = i >= ibeg && i < r1;
 #pragma unroll
       for (int c = 0; c < CPW; ++c)
-        g[q][c] = (ok && c < nj) ? __builtin_nontemporal_load(G + c * m + i) : T(0);
+        g[q][c] = (ok && c < nj) ? panel_load<NT>(G + c * m + i) : T(0);
     }
   }
   // inputs: own rows need dinv y, struct rows -x; a tile that lies in one
@@ -519,33 +528,37 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
-                    int tile_cols) {
+                    int tile_cols, bool stream) {
   if (n_tiles <= 0) return;
+#define FE_FWD(TC)                                                                           \
+  (stream ? k_tri_fwd<T, TC, true><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state) \
+          : k_tri_fwd<T, TC, false><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state))
   switch (tile_cols) {
-    case 16: k_tri_fwd<T, 16><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
-    case 32: k_tri_fwd<T, 32><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
-    case 64: k_tri_fwd<T, 64><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
-    case 128: k_tri_fwd<T, 128><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state); break;
+    case 16: FE_FWD(16); break;
+    case 32: FE_FWD(32); break;
+    case 64: FE_FWD(64); break;
+    case 128: FE_FWD(128); break;
     default: throw std::runtime_error("forward tile width must be 16, 32, 64 or 128");
   }
+#undef FE_FWD
 }
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state, int tile_rows) {
+                    const PcgState *state, int tile_rows, bool stream) {
   if (n_tiles <= 0) return;
+#define FE_BWD(BR)                                                                             \
+  (stream ? k_tri_bwd<T, BR, true><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, \
+                                                            state)                          \
+          : k_tri_bwd<T, BR, false><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, \
+                                                             state))
   switch (tile_rows) {
-    case 256:
-      k_tri_bwd<T, 256><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
-      break;
-    case 512:
-      k_tri_bwd<T, 512><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
-      break;
-    case 1024:
-      k_tri_bwd<T, 1024><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, state);
-      break;
+    case 256: FE_BWD(256); break;
+    case 512: FE_BWD(512); break;
+    case 1024: FE_BWD(1024); break;
     default: throw std::runtime_error("backward tile height must be 256, 512 or 1024");
   }
+#undef FE_BWD
 }
 
 #define FE_INST(T)                                                                             \
@@ -561,10 +574,11 @@ void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
   template void launch_tri_prep<T>(hipStream_t, int64_t, const double *, T *, T *, double *,   \
                                    const uint8_t *, const PcgState *);                         \
   template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int,            \
-                                  const int32_t *, const T *, T *, T *, const PcgState *, int);\
+                                  const int32_t *, const T *, T *, T *, const PcgState *, int,  \
+                                  bool);                                                       \
   template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, const T *, const T *, double *,  \
-                                  const PcgState *, int);
+                                  const PcgState *, int, bool);
 FE_INST(float)
 FE_INST(double)
 #undef FE_INST

@@ -168,7 +168,8 @@ void launch_ctl_init(hipStream_t st, PcgState *s, const double *part_rr, const d
 void launch_dot(hipStream_t st, int64_t n, const double *a, const double *b, double *part,
                 const PcgState *state);
 void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int first);
-void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np);
+void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np,
+                      double *stage = nullptr);
 void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np);
 void launch_update_p(hipStream_t st, int64_t n, double *p, const double *z, const PcgState *state,
                      int first);

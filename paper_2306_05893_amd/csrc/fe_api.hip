@@ -575,7 +575,9 @@ void cg_iteration(fe_ctx *c, const T *A, double *x, hipStream_t st) {
   const bool tri = c->active_slot >= 0;
   int np = 0;
   spmv<T>(c, A, c->d_p, c->d_q, c->d_p, c->d_part1, &np, st, c->d_state);
-  launch_ctl_alpha(st, c->d_state, c->d_part1, np);
+  // the SpMV's partials are summed in two stages, the first into part2
+  // (free until the update below writes its own partials there)
+  launch_ctl_alpha(st, c->d_state, c->d_part1, np, c->d_part2);
   launch_update_xr_prep<T>(st, n, x, c->d_r, c->d_p, c->d_q, c->d_part2, c->d_state,
                            tri ? (T *)c->d_w : nullptr, (T *)c->d_y, c->d_z, c->d_dof_fixed);
   launch_ctl_rr(st, c->d_state, c->d_part2, cg_blocks(n));

@@ -150,6 +150,22 @@ __global__ __launch_bounds__(kBlock) void k_ctl_rz(PcgState *s, const double *pa
   }
 }
 
+// First stage of a long partial sum: block b adds in[b * kPartChunk ..) in a
+// fixed order (each thread a strided run, then the block's tree) into
+// out[b], so that the one-block control kernel after it sums a few dozen
+// values instead of one per SpMV block (87 k on the largest mesh).
+constexpr int kPartChunk = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_part_reduce(const double *in, int n, double *out,
+                                                        const PcgState *s) {
+  if (s->done) return;
+  const int64_t lo = (int64_t)blockIdx.x * kPartChunk, hi = min((int64_t)n, lo + kPartChunk);
+  double t = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) t += in[i];
+  t = block_sum(t);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
 __global__ __launch_bounds__(kBlock) void k_ctl_alpha(PcgState *s, const double *part, int np) {
   if (s->done) return;
   const double pAp = sum_parts(part, np);
@@ -489,8 +505,14 @@ void launch_dot(hipStream_t st, int64_t n, const double *a, const double *b, dou
 void launch_ctl_rz(hipStream_t st, PcgState *s, const double *part, int np, int first) {
   k_ctl_rz<<<1, kBlock, 0, st>>>(s, part, np, first);
 }
-void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np) {
-  k_ctl_alpha<<<1, kBlock, 0, st>>>(s, part, np);
+void launch_ctl_alpha(hipStream_t st, PcgState *s, const double *part, int np, double *stage) {
+  if (stage && np > 4 * kPartChunk) {
+    const int nb = (np + kPartChunk - 1) / kPartChunk;
+    k_part_reduce<<<nb, kBlock, 0, st>>>(part, np, stage, s);
+    k_ctl_alpha<<<1, kBlock, 0, st>>>(s, stage, nb);
+  } else {
+    k_ctl_alpha<<<1, kBlock, 0, st>>>(s, part, np);
+  }
 }
 void launch_ctl_rr(hipStream_t st, PcgState *s, const double *part, int np) {
   k_ctl_rr<<<1, kBlock, 0, st>>>(s, part, np);

@@ -109,11 +109,13 @@ def _leg(r):
             "factor_lag_mean": round(r["factor_lag_mean"], 1)}
 
 
-# kernel names as rocprofv3 reports them (default tile extents 64 / 512; the
-# sweeps of the hex block and the hex beam read their panels non-temporally,
-# both factors being larger than the last-level cache)
-KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd<float, 64, true>",
-                 "trisolve_bwd": "k_tri_bwd<float, 512, true>",
+# kernel names as rocprofv3 reports them.  The sweeps are named by family:
+# their tile extents are chosen per level (forward k_tri_fwd<float, 64 or 128,
+# true>, backward k_tri_bwd<float, 256 or 512, true>; the third argument: the
+# panels of the hex block and the hex beam are read non-temporally, both
+# factors being larger than the last-level cache), and a sweep's figures are
+# averages over all its level launches.
+KERNEL_SYMBOL = {"trisolve_fwd": "k_tri_fwd", "trisolve_bwd": "k_tri_bwd",
                  "spmv": "k_spmv<float, 16>", "element": "k_elem_hex<float, 1, true>"}
 
 
@@ -172,14 +174,15 @@ def _roofline(kt, workload):
 
 
 def _recorded_traffic(workload, symbol):
-    """HBM bytes per launch from the committed PMC record, or None when the
-    kernel source has changed since the counters were taken."""
+    """HBM bytes per launch from the committed PMC record, or None when a
+    source it depends on (the kernels, the tile schedule) has changed since
+    the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(_traffic_record(workload)))
-        src = os.path.join(ROOT, rec["kernel_source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernel_source_sha256"]:
-            return None
+        for path, digest in rec["sources_sha256"].items():
+            if hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest() != digest:
+                return None
         return round(rec["kernels"][symbol]["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None

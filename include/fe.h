@@ -97,8 +97,12 @@ typedef struct {
 
 typedef struct {
   int32_t leaf_nodes;         /* nested-dissection leaf size in nodes (0: 48) */
-  int32_t fwd_tile_cols;      /* forward-sweep tile width 16/32/64/128 (0: 64) */
-  int32_t bwd_tile_rows;      /* backward tile height 256/512/1024 (0: 512)   */
+  int32_t fwd_tile_cols;      /* forward-sweep tile width 16/32/64/128 for every
+                                 level; 0: chosen per level (64, or 128 on levels
+                                 of supernodes with 65..128 own columns)       */
+  int32_t bwd_tile_rows;      /* backward tile height 256/512/1024 for every
+                                 level; 0: chosen per level (512, or 256 where
+                                 it pads the level's panel rows clearly less) */
   int32_t factor_on_gpu;      /* 1: fe_factor_async runs the FP64 multifrontal
                                  LDL^T on the GPU (own stream, writes the idle
                                  factor slot directly; no host round trip);

@@ -474,14 +474,14 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
   for (int L = 0; L < S.n_levels; ++L) {
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
-    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_cols,
+    launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_level_cols[L],
                       c->panel_stream);
   }
-  for (int L = 0; L < S.n_levels; ++L) {
+  for (int L = 0; L < S.n_levels; ++L) {  // L-th backward launch: level n_levels - 1 - L
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
     launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_rows, pan, dinv, y, z, s,
-                      S.bwd_rows, c->panel_stream);
+                      S.bwd_level_rows[S.n_levels - 1 - L], c->panel_stream);
   }
   if (c->rot_on) launch_rot_out<T>(st, n / 3, (const T *)c->d_rotQ, z, s);
 }

@@ -130,7 +130,8 @@ struct Symbolic {
   // GPU schedules, grouped by level (forward: ascending, backward: descending)
   std::vector<Tile> fwd_tiles, bwd_tiles;
   std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
-  int32_t fwd_cols = 0, bwd_rows = 0;  // tile extents in use
+  // tile extents per level (index = level): forward columns, backward rows
+  std::vector<int32_t> fwd_level_cols, bwd_level_rows;
   // many-right-hand-side schedules (same level order)
   std::vector<MTile> mfwd_tiles, mbwd_tiles;
   std::vector<int32_t> mfwd_level_ptr, mbwd_level_ptr;
@@ -142,7 +143,9 @@ struct Symbolic {
 constexpr int kFwdRows = 256;      // rows per forward tile (one per thread)
 constexpr int kBwdCols = 16;       // columns per backward tile (4 per wavefront)
 // columns per forward tile: 16, 32, 64 or 128; rows per backward tile: 256,
-// 512 or 1024 (compile-time extents of the sweep kernels)
+// 512 or 1024 (compile-time extents of the sweep kernels).  A requested
+// extent of 0 lets the analysis choose one per level from the level's
+// supernode shapes (tile_extents_for_level).
 inline bool valid_fwd_cols(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
 inline bool valid_bwd_rows(int r) { return r == 256 || r == 512 || r == 1024; }
 

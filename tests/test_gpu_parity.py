@@ -130,6 +130,30 @@ def test_preconditioner_parity(mesh, prec):
     assert _rel(z, z_host) <= (1e-11 if prec == 0 else 1e-5)
 
 
+@pytest.mark.parametrize("extents", [(16, 256), (32, 1024), (128, 512), (64, 256), (0, 0)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_preconditioner_parity_tile_extents(extents, prec):
+    """Every sweep tile shape (and the per-level choice, extents 0) gives the
+    same z = P^{-1} r as the oracle's banded solve with A_t0."""
+    w = synth.make("hex_diff")
+    q, v = _state(w)
+    ref = step.assemble(w, q, v)
+    fc, br = extents
+    print(f"[ctx] {w.name} prec={prec} fwd_tile_cols={fc} bwd_tile_rows={br}", flush=True)
+    ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec=prec, device=DEV,
+                    fwd_tile_cols=fc, bwd_tile_rows=br)
+    ctx.bind()
+    A, _ = ctx.assemble(_params(w), _t(q), _t(v))
+    ctx.factorize_now(A, 0)
+    r = synth.random_vector(w.n_dofs, 4)
+    z = ctx.precond_apply(_t(r)).cpu().numpy()
+    p = ref.pat
+    z_ref = solve.banded_cholesky_solve(p.n, p.row_ptr, p.col_idx, A.double().cpu().numpy(), r)
+    e = _rel(z, z_ref)
+    print(f"  precond err vs banded {e:.3e}")
+    assert e <= (1e-9 if prec == 0 else 1e-5)
+
+
 @pytest.mark.parametrize("mesh", ["tet_beam", "hex_diff"])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("use_factor", [True, False])

@@ -114,6 +114,11 @@ typedef struct {
                                  their work), i.e. on the share of the GPU the
                                  background refactorisation takes from the
                                  solves; 0: no bound                          */
+  int32_t bwd_tile_cols;      /* backward tile width 16/32/64 for every level
+                                 (4 columns per wavefront: 4, 8 or 16
+                                 wavefronts share a tile's gathered inputs);
+                                 0: chosen per level (64, or 32 where 64 pads
+                                 the level's own columns more)               */
 } fe_build_opts;
 
 /* Physical parameters of one assembly.  E and f_nodal are DEVICE pointers. */

@@ -105,7 +105,7 @@ void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state, int tile_rows, bool stream);
+                    const PcgState *state, int tile_rows, int tile_cols, bool stream);
 
 // Many right-hand sides: DOF-major n x ld blocks (ld = k rounded up to the
 // tile width bn, 64 or 128), w/y in the factor's precision, z FP64.

@@ -481,7 +481,8 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 2, c->bwd_level_bytes[L]);
     launch_tri_bwd<T>(st, c->d_btiles + b, e - b, c->d_rows, pan, dinv, y, z, s,
-                      S.bwd_level_rows[S.n_levels - 1 - L], c->panel_stream);
+                      S.bwd_level_rows[S.n_levels - 1 - L], S.bwd_level_cols[S.n_levels - 1 - L],
+                      c->panel_stream);
   }
   if (c->rot_on) launch_rot_out<T>(st, n / 3, (const T *)c->d_rotQ, z, s);
 }
@@ -1144,7 +1145,7 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
     if (e.empty()) {
       c->X.assign(mesh->X, mesh->X + 3 * (int64_t)mesh->n_nodes);
       e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, opts ? opts->fwd_tile_cols : 0,
-                  opts ? opts->bwd_tile_rows : 0, c->S);
+                  opts ? opts->bwd_tile_rows : 0, opts ? opts->bwd_tile_cols : 0, c->S);
     }
     if (e.empty() && opts && opts->factor_on_gpu) {
       c->gpu_factor = true;

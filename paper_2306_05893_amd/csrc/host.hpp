@@ -131,7 +131,7 @@ struct Symbolic {
   std::vector<Tile> fwd_tiles, bwd_tiles;
   std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
   // tile extents per level (index = level): forward columns, backward rows
-  std::vector<int32_t> fwd_level_cols, bwd_level_rows;
+  std::vector<int32_t> fwd_level_cols, bwd_level_rows, bwd_level_cols;
   // many-right-hand-side schedules (same level order)
   std::vector<MTile> mfwd_tiles, mbwd_tiles;
   std::vector<int32_t> mfwd_level_ptr, mbwd_level_ptr;
@@ -141,18 +141,19 @@ struct Symbolic {
 
 // Tile extents shared with the device kernels.
 constexpr int kFwdRows = 256;      // rows per forward tile (one per thread)
-constexpr int kBwdCols = 16;       // columns per backward tile (4 per wavefront)
+constexpr int kBwdColsPerWave = 4;  // backward tile: 4 columns per wavefront
 // columns per forward tile: 16, 32, 64 or 128; rows per backward tile: 256,
 // 512 or 1024 (compile-time extents of the sweep kernels).  A requested
 // extent of 0 lets the analysis choose one per level from the level's
 // supernode shapes (tile_extents_for_level).
 inline bool valid_fwd_cols(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
 inline bool valid_bwd_rows(int r) { return r == 256 || r == 512 || r == 1024; }
+inline bool valid_bwd_cols(int c) { return c == 16 || c == 32 || c == 64; }
 
 // Geometric nested dissection on the node graph, supernodes = ND blocks,
 // relaxed (dense) supernodal structure from the assembly tree.
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
-                    int32_t bwd_rows, Symbolic &S);
+                    int32_t bwd_rows, int32_t bwd_cols, Symbolic &S);
 
 // ------------------------------------------- GPU factorisation plan
 // One frontal matrix of the GPU multifrontal factorisation.  The front is

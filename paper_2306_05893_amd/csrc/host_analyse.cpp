@@ -160,13 +160,21 @@ struct Dissector {
 // tiles whose second is mostly empty, which halves the level's tiles, input
 // gathers and output atomics; other levels keep 64 (128 doubles the panel
 // registers of a thread and so halves the tiles in flight, for no measurable
-// gain on wide supernodes).  Backward: 256-row tiles where they cover the
-// level's panel rows with clearly less padding than 512-row tiles (supernodes
-// of a few hundred rows), else 512.  On the 1.39 M-DOF hex block this moves
-// levels 2 and 3 of the forward sweep from 100 and 79 us to 81 and 67 us,
-// and level 2 of the backward sweep from 113 to 93 us.
+// gain on wide supernodes).  Backward rows: 256-row tiles where they cover
+// the level's panel rows with clearly less padding than 512-row tiles
+// (supernodes of a few hundred rows), else 512.  Backward columns: the widest
+// of 64 and 32 (16 and 8 wavefronts sharing the tile's gathered inputs) that
+// pads the level's own columns by at most 5 % more than 32 does and still
+// gives the level kSweepMinTiles workgroups (4 per compute unit), else 16:
+// a small level is bound by the latency of its tiles, and fewer, wider tiles
+// only lengthen it (the 14,883-DOF beam ran 6 % slower with them).  On the
+// 1.39 M-DOF hex block: forward levels 2 and 3 100 -> 81 and 79 -> 67 us,
+// backward level 2 113 -> 93 us; the backward sweep 2.22 -> 2.02 ms with
+// 32-column instead of 16-column tiles, and about 0.03 ms less with 64
+// columns on its wide levels.
+constexpr double kSweepMinTiles = 1024;
 static void tile_extents_for_level(const Symbolic &S, const std::vector<int32_t> &sns,
-                                   int32_t &fwd_cols, int32_t &bwd_rows) {
+                                   int32_t &fwd_cols, int32_t &bwd_rows, int32_t &bwd_cols) {
   if (fwd_cols == 0) {
     size_t mid = 0;
     for (int32_t s : sns) mid += S.sn[s].nc > 64 && S.sn[s].nc <= 128;
@@ -182,6 +190,20 @@ static void tile_extents_for_level(const Symbolic &S, const std::vector<int32_t>
     }
     // fill(256) > 1.1 fill(512)  <=>  1.1 pad256 < pad512
     bwd_rows = m > 0 && 1.1 * pad256 < pad512 ? 256 : 512;
+  }
+  if (bwd_cols == 0) {
+    double pad32 = 0, pad64 = 0, tiles32 = 0, tiles64 = 0;
+    for (int32_t s : sns) {
+      const double c = S.sn[s].nc, rb = std::ceil(S.sn[s].m / (double)bwd_rows);
+      pad32 += 32.0 * std::ceil(c / 32.0);
+      pad64 += 64.0 * std::ceil(c / 64.0);
+      tiles32 += rb * std::ceil(c / 32.0);
+      tiles64 += rb * std::ceil(c / 64.0);
+    }
+    // wide tiles only where the level still has kSweepMinTiles of them
+    if (pad64 <= 1.05 * pad32 && tiles64 >= kSweepMinTiles) bwd_cols = 64;
+    else if (tiles32 >= kSweepMinTiles) bwd_cols = 32;
+    else bwd_cols = 16;
   }
 }
 
@@ -236,12 +258,12 @@ static void build_multi_tiles(Symbolic &S, const std::vector<std::vector<int32_t
 }
 
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
-                    int32_t bwd_rows, Symbolic &S) {
+                    int32_t bwd_rows, int32_t bwd_cols, Symbolic &S) {
   if (leaf_nodes <= 0) leaf_nodes = 48;
-  if (fwd_cols < 0 || bwd_rows < 0 || (fwd_cols && !valid_fwd_cols(fwd_cols)) ||
-      (bwd_rows && !valid_bwd_rows(bwd_rows)))
+  if (fwd_cols < 0 || bwd_rows < 0 || bwd_cols < 0 || (fwd_cols && !valid_fwd_cols(fwd_cols)) ||
+      (bwd_rows && !valid_bwd_rows(bwd_rows)) || (bwd_cols && !valid_bwd_cols(bwd_cols)))
     return "tile extents: forward width 0, 16, 32, 64 or 128; backward height 0, 256, 512 or "
-           "1024 (0: chosen per level)";
+           "1024; backward width 0, 16, 32 or 64 (0: chosen per level)";
   const int32_t N = P.n_nodes;
   S = Symbolic();
   S.n = P.n;
@@ -400,8 +422,10 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
   S.bwd_level_ptr.assign(1, 0);
   S.fwd_level_cols.assign(nl, fwd_cols);
   S.bwd_level_rows.assign(nl, bwd_rows);
+  S.bwd_level_cols.assign(nl, bwd_cols);
   for (int32_t L = 0; L < nl; ++L)
-    tile_extents_for_level(S, by_level[L], S.fwd_level_cols[L], S.bwd_level_rows[L]);
+    tile_extents_for_level(S, by_level[L], S.fwd_level_cols[L], S.bwd_level_rows[L],
+                           S.bwd_level_cols[L]);
   for (int32_t L = 0; L < nl; ++L) {
     const int32_t fwd_cols_L = S.fwd_level_cols[L];
     for (int32_t s : by_level[L]) {
@@ -416,10 +440,10 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
     S.fwd_level_ptr.push_back((int32_t)S.fwd_tiles.size());
   }
   for (int32_t L = nl - 1; L >= 0; --L) {
-    const int32_t bwd_rows_L = S.bwd_level_rows[L];
+    const int32_t bwd_rows_L = S.bwd_level_rows[L], bwd_cols_L = S.bwd_level_cols[L];
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
-      for (int32_t c0 = 0; c0 < sn.nc; c0 += kBwdCols)
+      for (int32_t c0 = 0; c0 < sn.nc; c0 += bwd_cols_L)
         for (int32_t r0 = 0; r0 < sn.m; r0 += bwd_rows_L) {
           const int32_t r1 = std::min(sn.m, r0 + bwd_rows_L);
           if (r1 <= c0) continue;

@@ -282,7 +282,7 @@ __global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
 }
 
 constexpr int kFR = 256;  // forward tile: 256 rows x TC columns (TC: 16..128)
-constexpr int kBC = kBwdCols;  // backward tile: kBC columns x BR rows (BR: 256..1024)
+// backward tile: 4 NW columns x BR rows (BR: 256..1024), NW wavefronts of 4 columns
 
 // Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
 // rows (one row per thread, consecutive rows = consecutive addresses of the
@@ -360,11 +360,12 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
 
 // Backward tile: x[rows[j]] += sum_{i in tile rows} G[i, j] v_i with
 // v_i = dinv y (own rows) or -x[rows[i]] (struct rows, already final).
-// Each wavefront handles CPW consecutive columns (lanes stride over rows)
-// and issues all BR/64 x CPW of its panel loads before the inputs v are
-// gathered.  Rows above a column's diagonal (zeros of L11^{-1}) are not read.
-template <typename T, int BR, bool NT>
-__global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ tiles,
+// Each of the NW wavefronts handles CPW = 4 consecutive columns (lanes stride
+// over rows) and issues all BR/64 x CPW of its panel loads before the inputs
+// v are gathered; the workgroup gathers the BR inputs once for its 4 NW
+// columns.  Rows above a column's diagonal (zeros of L11^{-1}) are not read.
+template <typename T, int BR, bool NT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_tri_bwd(const TileDev *__restrict__ tiles,
                                                  const int32_t *__restrict__ rows,
                                                  const T *__restrict__ panels,
                                                  const T *__restrict__ dinv,
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   asm volatile("" ::"s"(d.panel_off), "s"(d.rows_off), "s"(d.nc), "s"(d.m), "s"(rows),
                "s"(panels));
   if (done) return;
-  constexpr int NI = BR / 64, CPW = kBC / 4;
+  constexpr int NI = BR / 64, CPW = kBwdColsPerWave, NTH = 64 * NW;
   __shared__ T s_v[BR];
   const TileDev &t = d;
   const int32_t *rw = rows + d.rows_off;
@@ -388,10 +389,10 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   const T *G = panels + d.panel_off + (int64_t)min(j0, d.nc - 1) * m;
   // index loads of the inputs first (clamped, unconditional), then the panel
   // loads, then the input values
-  constexpr int NV = BR / 256;
+  constexpr int NV = (BR + NTH - 1) / NTH;
   int32_t dof[NV];
 #pragma unroll
-  for (int u = 0; u < NV; ++u) dof[u] = rw[min(r0 + (int)threadIdx.x + 256 * u, r1 - 1)];
+  for (int u = 0; u < NV; ++u) dof[u] = rw[min(r0 + (int)threadIdx.x + NTH * u, r1 - 1)];
   T g[NI][CPW];
   if (nj == CPW && ibeg == r0 && r1 == r0 + BR) {
 #pragma unroll
@@ -415,7 +416,8 @@ __global__ __launch_bounds__(256) void k_tri_bwd(const TileDev *__restrict__ til
   const int mode = r0 >= d.nc ? 1 : (r1 <= d.nc ? 0 : 2);
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
-    const int k = (int)threadIdx.x + 256 * u, i = r0 + k;
+    const int k = (int)threadIdx.x + NTH * u, i = r0 + k;
+    if (NTH * (u + 1) > BR && k >= BR) break;  // (compile-time false unless NTH > BR)
     T v;
     if (mode == 0) {
       v = dinv[dof[u]] * y[dof[u]];
@@ -567,19 +569,30 @@ void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,
-                    const PcgState *state, int tile_rows, bool stream) {
+                    const PcgState *state, int tile_rows, int tile_cols, bool stream) {
   if (n_tiles <= 0) return;
-#define FE_BWD(BR)                                                                             \
-  (stream ? k_tri_bwd<T, BR, true><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, \
-                                                            state)                          \
-          : k_tri_bwd<T, BR, false><<<n_tiles, 256, 0, st>>>(tiles, rows, panels, dinv, y, z, \
-                                                             state))
-  switch (tile_rows) {
-    case 256: FE_BWD(256); break;
-    case 512: FE_BWD(512); break;
-    case 1024: FE_BWD(1024); break;
-    default: throw std::runtime_error("backward tile height must be 256, 512 or 1024");
+#define FE_BWD(BR, NW)                                                                       \
+  (stream ? k_tri_bwd<T, BR, true, NW><<<n_tiles, 64 * NW, 0, st>>>(tiles, rows, panels,    \
+                                                                   dinv, y, z, state)       \
+          : k_tri_bwd<T, BR, false, NW><<<n_tiles, 64 * NW, 0, st>>>(tiles, rows, panels,   \
+                                                                    dinv, y, z, state))
+#define FE_BWD_ROWS(NW)                                                                     \
+  switch (tile_rows) {                                                                      \
+    case 256: FE_BWD(256, NW); break;                                                       \
+    case 512: FE_BWD(512, NW); break;                                                       \
+    case 1024: FE_BWD(1024, NW); break;                                                     \
+    default: throw std::runtime_error("backward tile height must be 256, 512 or 1024");     \
   }
+  if (tile_cols == 4 * kBwdColsPerWave) {
+    FE_BWD_ROWS(4)
+  } else if (tile_cols == 8 * kBwdColsPerWave) {
+    FE_BWD_ROWS(8)
+  } else if (tile_cols == 16 * kBwdColsPerWave) {
+    FE_BWD_ROWS(16)
+  } else {
+    throw std::runtime_error("backward tile width must be 16, 32 or 64");
+  }
+#undef FE_BWD_ROWS
 #undef FE_BWD
 }
 
@@ -600,7 +613,7 @@ void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                                   bool);                                                       \
   template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, const T *, const T *, double *,  \
-                                  const PcgState *, int, bool);
+                                  const PcgState *, int, int, bool);
 FE_INST(float)
 FE_INST(double)
 #undef FE_INST

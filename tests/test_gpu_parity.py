@@ -130,7 +130,8 @@ def test_preconditioner_parity(mesh, prec):
     assert _rel(z, z_host) <= (1e-11 if prec == 0 else 1e-5)
 
 
-@pytest.mark.parametrize("extents", [(16, 256), (32, 1024), (128, 512), (64, 256), (0, 0)])
+@pytest.mark.parametrize("extents", [(16, 256, 16), (32, 1024, 32), (128, 512, 16), (64, 256, 32),
+                                     (0, 0, 0), (0, 0, 32), (64, 1024, 64)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_preconditioner_parity_tile_extents(extents, prec):
     """Every sweep tile shape (and the per-level choice, extents 0) gives the
@@ -138,10 +139,11 @@ def test_preconditioner_parity_tile_extents(extents, prec):
     w = synth.make("hex_diff")
     q, v = _state(w)
     ref = step.assemble(w, q, v)
-    fc, br = extents
-    print(f"[ctx] {w.name} prec={prec} fwd_tile_cols={fc} bwd_tile_rows={br}", flush=True)
+    fc, br, bc = extents
+    print(f"[ctx] {w.name} prec={prec} fwd_tile_cols={fc} bwd_tile_rows={br} bwd_tile_cols={bc}",
+          flush=True)
     ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec=prec, device=DEV,
-                    fwd_tile_cols=fc, bwd_tile_rows=br)
+                    fwd_tile_cols=fc, bwd_tile_rows=br, bwd_tile_cols=bc)
     ctx.bind()
     A, _ = ctx.assemble(_params(w), _t(q), _t(v))
     ctx.factorize_now(A, 0)

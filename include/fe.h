@@ -119,6 +119,11 @@ typedef struct {
                                  wavefronts share a tile's gathered inputs);
                                  0: chosen per level (64, or 32 where 64 pads
                                  the level's own columns more)               */
+  int32_t fwd_col_groups;     /* forward tiles of 1, 2 or 4 groups of 64
+                                 columns (4 wavefronts each) whose row sums
+                                 meet in one atomic, on every 64-column level;
+                                 0: chosen per level (4 on levels of wide
+                                 supernodes, else 1)                         */
 } fe_build_opts;
 
 /* Physical parameters of one assembly.  E and f_nodal are DEVICE pointers. */

@@ -47,7 +47,7 @@ class fe_build_opts(C.Structure):
     _fields_ = [("leaf_nodes", C.c_int32), ("fwd_tile_cols", C.c_int32),
                 ("bwd_tile_rows", C.c_int32), ("factor_on_gpu", C.c_int32),
                 ("n_threads", C.c_int32), ("factor_max_blocks", C.c_int32),
-                ("bwd_tile_cols", C.c_int32)]
+                ("bwd_tile_cols", C.c_int32), ("fwd_col_groups", C.c_int32)]
 
 
 class fe_params(C.Structure):

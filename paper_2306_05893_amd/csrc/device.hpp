@@ -101,7 +101,7 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
-                    int tile_cols, bool stream);
+                    int tile_cols, int groups, bool stream);
 template <typename T>
 void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, const T *dinv, const T *y, double *z,

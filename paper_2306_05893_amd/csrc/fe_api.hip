@@ -475,7 +475,7 @@ void precond(fe_ctx *c, const T *A, const double *r, double *z, hipStream_t st, 
     const int b = S.fwd_level_ptr[L], e = S.fwd_level_ptr[L + 1];
     TimedLaunch tl(c, st, 1, c->fwd_level_bytes[L]);
     launch_tri_fwd<T>(st, c->d_ftiles + b, e - b, c->d_rows, pan, w, y, s, S.fwd_level_cols[L],
-                      c->panel_stream);
+                      S.fwd_level_groups[L], c->panel_stream);
   }
   for (int L = 0; L < S.n_levels; ++L) {  // L-th backward launch: level n_levels - 1 - L
     const int b = S.bwd_level_ptr[L], e = S.bwd_level_ptr[L + 1];
@@ -1145,7 +1145,8 @@ int fe_build_pattern(const fe_mesh *mesh, const uint8_t *fixed_dof, const fe_bui
     if (e.empty()) {
       c->X.assign(mesh->X, mesh->X + 3 * (int64_t)mesh->n_nodes);
       e = analyse(c->P, c->X.data(), opts ? opts->leaf_nodes : 0, opts ? opts->fwd_tile_cols : 0,
-                  opts ? opts->bwd_tile_rows : 0, opts ? opts->bwd_tile_cols : 0, c->S);
+                  opts ? opts->fwd_col_groups : 0, opts ? opts->bwd_tile_rows : 0,
+                  opts ? opts->bwd_tile_cols : 0, c->S);
     }
     if (e.empty() && opts && opts->factor_on_gpu) {
       c->gpu_factor = true;

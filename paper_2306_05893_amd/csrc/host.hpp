@@ -131,7 +131,7 @@ struct Symbolic {
   std::vector<Tile> fwd_tiles, bwd_tiles;
   std::vector<int32_t> fwd_level_ptr, bwd_level_ptr;
   // tile extents per level (index = level): forward columns, backward rows
-  std::vector<int32_t> fwd_level_cols, bwd_level_rows, bwd_level_cols;
+  std::vector<int32_t> fwd_level_cols, fwd_level_groups, bwd_level_rows, bwd_level_cols;
   // many-right-hand-side schedules (same level order)
   std::vector<MTile> mfwd_tiles, mbwd_tiles;
   std::vector<int32_t> mfwd_level_ptr, mbwd_level_ptr;
@@ -153,7 +153,7 @@ inline bool valid_bwd_cols(int c) { return c == 16 || c == 32 || c == 64; }
 // Geometric nested dissection on the node graph, supernodes = ND blocks,
 // relaxed (dense) supernodal structure from the assembly tree.
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
-                    int32_t bwd_rows, int32_t bwd_cols, Symbolic &S);
+                    int32_t fwd_groups, int32_t bwd_rows, int32_t bwd_cols, Symbolic &S);
 
 // ------------------------------------------- GPU factorisation plan
 // One frontal matrix of the GPU multifrontal factorisation.  The front is

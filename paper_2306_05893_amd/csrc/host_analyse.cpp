@@ -159,8 +159,12 @@ struct Dissector {
 // columns takes 128-column tiles, one per row block instead of two 64-column
 // tiles whose second is mostly empty, which halves the level's tiles, input
 // gathers and output atomics; other levels keep 64 (128 doubles the panel
-// registers of a thread and so halves the tiles in flight, for no measurable
-// gain on wide supernodes).  Backward rows: 256-row tiles where they cover
+// registers of a thread and so halves the tiles in flight).  A level of wide
+// supernodes (256-column tiles pad its own columns by at most 10 % more than
+// 64-column ones, and it keeps kSweepMinTiles tiles) takes 4 groups of 64
+// columns per tile, whose row sums meet in one atomic per row: a quarter of
+// the atomics (forward levels 8-12 of the hex block 3-4 % faster; on narrow
+// supernodes the empty groups only cost).  Backward rows: 256-row tiles where they cover
 // the level's panel rows with clearly less padding than 512-row tiles
 // (supernodes of a few hundred rows), else 512.  Backward columns: the widest
 // of 64 and 32 (16 and 8 wavefronts sharing the tile's gathered inputs) that
@@ -174,11 +178,24 @@ struct Dissector {
 // columns on its wide levels.
 constexpr double kSweepMinTiles = 1024;
 static void tile_extents_for_level(const Symbolic &S, const std::vector<int32_t> &sns,
-                                   int32_t &fwd_cols, int32_t &bwd_rows, int32_t &bwd_cols) {
+                                   int32_t &fwd_cols, int32_t &fwd_groups, int32_t &bwd_rows,
+                                   int32_t &bwd_cols) {
   if (fwd_cols == 0) {
     size_t mid = 0;
     for (int32_t s : sns) mid += S.sn[s].nc > 64 && S.sn[s].nc <= 128;
     fwd_cols = 2 * mid >= sns.size() && !sns.empty() ? 128 : 64;
+  }
+  if (fwd_cols != 64) {
+    fwd_groups = 1;  // column groups are groups of 64 columns
+  } else if (fwd_groups == 0) {
+    double pad64 = 0, pad256 = 0, tiles256 = 0;
+    for (int32_t s : sns) {
+      const double c = S.sn[s].nc, rb = std::ceil(S.sn[s].m / (double)kFwdRows);
+      pad64 += 64.0 * std::ceil(c / 64.0);
+      pad256 += 256.0 * std::ceil(c / 256.0);
+      tiles256 += rb * std::ceil(c / 256.0);
+    }
+    fwd_groups = pad256 <= 1.1 * pad64 && tiles256 >= kSweepMinTiles ? 4 : 1;
   }
   if (bwd_rows == 0) {
     double m = 0, pad256 = 0, pad512 = 0;
@@ -258,8 +275,11 @@ static void build_multi_tiles(Symbolic &S, const std::vector<std::vector<int32_t
 }
 
 std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32_t fwd_cols,
-                    int32_t bwd_rows, int32_t bwd_cols, Symbolic &S) {
+                    int32_t fwd_groups, int32_t bwd_rows, int32_t bwd_cols, Symbolic &S) {
   if (leaf_nodes <= 0) leaf_nodes = 48;
+  if (fwd_groups < 0 || fwd_groups == 3 || fwd_groups > 4 ||
+      (fwd_groups > 1 && fwd_cols != 0 && fwd_cols != 64))
+    return "forward column groups: 0 (chosen per level), 1, 2 or 4 (groups of 64 columns)";
   if (fwd_cols < 0 || bwd_rows < 0 || bwd_cols < 0 || (fwd_cols && !valid_fwd_cols(fwd_cols)) ||
       (bwd_rows && !valid_bwd_rows(bwd_rows)) || (bwd_cols && !valid_bwd_cols(bwd_cols)))
     return "tile extents: forward width 0, 16, 32, 64 or 128; backward height 0, 256, 512 or "
@@ -421,13 +441,14 @@ std::string analyse(const Pattern &P, const double *X, int32_t leaf_nodes, int32
   S.fwd_level_ptr.assign(1, 0);
   S.bwd_level_ptr.assign(1, 0);
   S.fwd_level_cols.assign(nl, fwd_cols);
+  S.fwd_level_groups.assign(nl, fwd_groups);
   S.bwd_level_rows.assign(nl, bwd_rows);
   S.bwd_level_cols.assign(nl, bwd_cols);
   for (int32_t L = 0; L < nl; ++L)
-    tile_extents_for_level(S, by_level[L], S.fwd_level_cols[L], S.bwd_level_rows[L],
-                           S.bwd_level_cols[L]);
+    tile_extents_for_level(S, by_level[L], S.fwd_level_cols[L], S.fwd_level_groups[L],
+                           S.bwd_level_rows[L], S.bwd_level_cols[L]);
   for (int32_t L = 0; L < nl; ++L) {
-    const int32_t fwd_cols_L = S.fwd_level_cols[L];
+    const int32_t fwd_cols_L = S.fwd_level_cols[L] * S.fwd_level_groups[L];
     for (int32_t s : by_level[L]) {
       const Supernode &sn = S.sn[s];
       for (int32_t r0 = 0; r0 < sn.m; r0 += kFwdRows)

@@ -304,11 +304,11 @@ __device__ inline T panel_load(const T *p) {
   else return *p;
 }
 
-template <typename T, int TC, bool NT>
-__global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ tiles,
-                                                 const int32_t *__restrict__ rows,
-                                                 const T *__restrict__ panels, T *w, T *y,
-                                                 const PcgState *s) {
+template <typename T, int TC, bool NT, int NG>
+__global__ __launch_bounds__(kFR * NG) void k_tri_fwd(const TileDev *__restrict__ tiles,
+                                                      const int32_t *__restrict__ rows,
+                                                      const T *__restrict__ panels, T *w, T *y,
+                                                      const PcgState *s) {
   // the descriptor, the control word and the kernel arguments are loaded
   // together, one latency before the index and panel loads (the empty asm
   // takes the values the tile needs, so that the compiler does not sink
@@ -318,21 +318,25 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
   asm volatile("" ::"s"(d.panel_off), "s"(d.rows_off), "s"(d.nc), "s"(d.m), "s"(rows),
                "s"(panels));
   if (done) return;
-  __shared__ T s_in[TC];
+  __shared__ T s_in[NG][TC];
+  __shared__ T s_part[NG > 1 ? NG - 1 : 1][kFR];
   const TileDev &t = d;
   const int32_t *rw = rows + d.rows_off;
-  const int c0 = t.c0, ncol = min(d.nc - c0, TC);
-  const int tid = (int)threadIdx.x;
-  const int i = t.r0 + tid;
+  const int tid = (int)threadIdx.x, r = tid % kFR, grp = tid / kFR;
+  // group grp (4 wavefronts) takes columns c0 .. c0 + TC - 1 of the tile;
+  // a group past the supernode's last column has ncol <= 0 and loads nothing
+  const int c0 = t.c0 + grp * TC, ncol = min(d.nc - c0, TC);
+  const int i = t.r0 + r;
   const bool valid = i < d.m;
-  // index loads first, unconditional (clamped), so that no wait separates
-  // them from the panel loads issued next
-  const int32_t din = rw[c0 + min(tid, ncol - 1)];
+  // index loads first, unconditional (clamped: c0 + min(r, ncol - 1) is at
+  // most nc - 1, also when ncol <= 0), so that no wait separates them from
+  // the panel loads issued next
+  const int32_t din = rw[c0 + min(r, ncol - 1)];
   const int32_t dout = rw[min(i, d.m - 1)];
-  // columns of this row inside the tile (own rows stop at the diagonal)
+  // columns of this row inside the group (own rows stop at the diagonal)
   const int lim = !valid ? 0 : (i < d.nc ? min(ncol, i + 1 - c0) : ncol);
   const int64_t m = d.ld;  // column stride
-  const T *G = panels + d.panel_off + (int64_t)c0 * m + (valid ? i : 0);
+  const T *G = panels + d.panel_off + (int64_t)min(c0, d.nc - 1) * m + (valid ? i : 0);
   const bool full = ncol == TC && t.r0 + kFR <= d.m && (t.r0 >= d.nc || t.r0 + 1 >= c0 + TC);
   T g[TC];
   if (full) {
@@ -342,18 +346,32 @@ __global__ __launch_bounds__(kFR) void k_tri_fwd(const TileDev *__restrict__ til
 #pragma unroll
     for (int j = 0; j < TC; ++j) g[j] = j < lim ? panel_load<NT>(G + j * m) : T(0);
   }
-  if (tid < TC) s_in[tid] = tid < ncol ? w[din] : T(0);
+  if (r < TC) s_in[grp][r] = r < ncol ? w[din] : T(0);
   __syncthreads();
-  if (lim <= 0) return;
-  T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+  T acc = T(0);
+  if (lim > 0) {
+    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-  for (int j = 0; j < TC; j += 4) {
-    a0 += g[j] * s_in[j];
-    a1 += g[j + 1] * s_in[j + 1];
-    a2 += g[j + 2] * s_in[j + 2];
-    a3 += g[j + 3] * s_in[j + 3];
+    for (int j = 0; j < TC; j += 4) {
+      a0 += g[j] * s_in[grp][j];
+      a1 += g[j + 1] * s_in[grp][j + 1];
+      a2 += g[j + 2] * s_in[grp][j + 2];
+      a3 += g[j + 3] * s_in[grp][j + 3];
+    }
+    acc = (a0 + a1) + (a2 + a3);
   }
-  const T acc = (a0 + a1) + (a2 + a3);
+  if constexpr (NG > 1) {
+    // the groups' partial sums of a row meet in group 0 (fixed order), so a
+    // row takes one atomic per NG TC columns
+    if (grp > 0) s_part[grp - 1][r] = acc;
+    __syncthreads();
+    if (grp > 0) return;
+#pragma unroll
+    for (int q = 0; q < NG - 1; ++q) acc += s_part[q][r];
+  }
+  // a row has entries in the tile unless it is an own row above the tile's
+  // first column
+  if (!valid || (i < d.nc && i < t.c0)) return;
   if (i < d.nc) atomicAdd(y + dout, acc);
   else atomicAdd(w + dout, -acc);
 }
@@ -552,17 +570,27 @@ void launch_tri_prep(hipStream_t st, int64_t n, const double *r, T *w, T *y, dou
 template <typename T>
 void launch_tri_fwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                     const int32_t *rows, const T *panels, T *w, T *y, const PcgState *state,
-                    int tile_cols, bool stream) {
+                    int tile_cols, int groups, bool stream) {
   if (n_tiles <= 0) return;
-#define FE_FWD(TC)                                                                           \
-  (stream ? k_tri_fwd<T, TC, true><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state) \
-          : k_tri_fwd<T, TC, false><<<n_tiles, kFR, 0, st>>>(tiles, rows, panels, w, y, state))
-  switch (tile_cols) {
-    case 16: FE_FWD(16); break;
-    case 32: FE_FWD(32); break;
-    case 64: FE_FWD(64); break;
-    case 128: FE_FWD(128); break;
-    default: throw std::runtime_error("forward tile width must be 16, 32, 64 or 128");
+#define FE_FWD(TC, NG)                                                                       \
+  (stream ? k_tri_fwd<T, TC, true, NG><<<n_tiles, kFR * NG, 0, st>>>(tiles, rows, panels, w, \
+                                                                     y, state)             \
+          : k_tri_fwd<T, TC, false, NG><<<n_tiles, kFR * NG, 0, st>>>(tiles, rows, panels,  \
+                                                                      w, y, state))
+  if (groups == 1) {
+    switch (tile_cols) {
+      case 16: FE_FWD(16, 1); break;
+      case 32: FE_FWD(32, 1); break;
+      case 64: FE_FWD(64, 1); break;
+      case 128: FE_FWD(128, 1); break;
+      default: throw std::runtime_error("forward tile width must be 16, 32, 64 or 128");
+    }
+  } else if (tile_cols == 64 && groups == 2) {
+    FE_FWD(64, 2);
+  } else if (tile_cols == 64 && groups == 4) {
+    FE_FWD(64, 4);
+  } else {
+    throw std::runtime_error("forward column groups: 2 or 4 groups of 64 columns");
   }
 #undef FE_FWD
 }
@@ -610,7 +638,7 @@ void launch_tri_bwd(hipStream_t st, const TileDev *tiles, int n_tiles,
                                    const uint8_t *, const PcgState *);                         \
   template void launch_tri_fwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, T *, T *, const PcgState *, int,  \
-                                  bool);                                                       \
+                                  int, bool);                                                       \
   template void launch_tri_bwd<T>(hipStream_t, const TileDev *, int,            \
                                   const int32_t *, const T *, const T *, const T *, double *,  \
                                   const PcgState *, int, int, bool);

@@ -106,7 +106,7 @@ class FEContext:
 
     def __init__(self, X, conn, elem_type, fixed=None, prec=L.FE_PREC_FP64, leaf_nodes=0,
                  n_threads=0, device="cuda", fwd_tile_cols=0, bwd_tile_rows=0,
-                 factor_on_gpu=False, factor_max_blocks=0, bwd_tile_cols=0):
+                 factor_on_gpu=False, factor_max_blocks=0, bwd_tile_cols=0, fwd_col_groups=0):
         self.lib = L.load()
         X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1)
         conn = np.ascontiguousarray(conn, dtype=np.int32).reshape(-1)
@@ -121,7 +121,7 @@ class FEContext:
             fx = fixed.ctypes.data_as(C.c_void_p)
         opts = L.fe_build_opts(int(leaf_nodes), int(fwd_tile_cols), int(bwd_tile_rows),
                                1 if factor_on_gpu else 0, int(n_threads), int(factor_max_blocks),
-                               int(bwd_tile_cols))
+                               int(bwd_tile_cols), int(fwd_col_groups))
         h = C.c_void_p()
         L.check(self.lib.fe_build_pattern(C.byref(mesh), fx, C.byref(opts), C.byref(h)), None)
         self.h = h
@@ -487,7 +487,7 @@ class Simulation:
     """
 
     def __init__(self, workload, prec=L.FE_PREC_FP64, device="cuda", leaf_nodes=0, n_threads=0,
-                 factor_on_gpu=False, factor_max_blocks=0, bwd_tile_cols=0):
+                 factor_on_gpu=False, factor_max_blocks=0, bwd_tile_cols=0, fwd_col_groups=0):
         w = workload
         self.w = w
         self.ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec, leaf_nodes, n_threads, device,

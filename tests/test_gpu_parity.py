@@ -130,8 +130,9 @@ def test_preconditioner_parity(mesh, prec):
     assert _rel(z, z_host) <= (1e-11 if prec == 0 else 1e-5)
 
 
-@pytest.mark.parametrize("extents", [(16, 256, 16), (32, 1024, 32), (128, 512, 16), (64, 256, 32),
-                                     (0, 0, 0), (0, 0, 32), (64, 1024, 64)])
+@pytest.mark.parametrize("extents", [(16, 256, 16, 1), (32, 1024, 32, 1), (128, 512, 16, 1),
+                                     (64, 256, 32, 2), (0, 0, 0, 0), (0, 0, 32, 4),
+                                     (64, 1024, 64, 4)])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_preconditioner_parity_tile_extents(extents, prec):
     """Every sweep tile shape (and the per-level choice, extents 0) gives the
@@ -139,11 +140,11 @@ def test_preconditioner_parity_tile_extents(extents, prec):
     w = synth.make("hex_diff")
     q, v = _state(w)
     ref = step.assemble(w, q, v)
-    fc, br, bc = extents
-    print(f"[ctx] {w.name} prec={prec} fwd_tile_cols={fc} bwd_tile_rows={br} bwd_tile_cols={bc}",
-          flush=True)
+    fc, br, bc, fg = extents
+    print(f"[ctx] {w.name} prec={prec} fwd_tile_cols={fc} fwd_col_groups={fg} "
+          f"bwd_tile_rows={br} bwd_tile_cols={bc}", flush=True)
     ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec=prec, device=DEV,
-                    fwd_tile_cols=fc, bwd_tile_rows=br, bwd_tile_cols=bc)
+                    fwd_tile_cols=fc, bwd_tile_rows=br, bwd_tile_cols=bc, fwd_col_groups=fg)
     ctx.bind()
     A, _ = ctx.assemble(_params(w), _t(q), _t(v))
     ctx.factorize_now(A, 0)

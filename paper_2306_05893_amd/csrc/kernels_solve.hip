@@ -338,27 +338,41 @@ __global__ __launch_bounds__(kFR * NG) void k_tri_fwd(const TileDev *__restrict_
   const int64_t m = d.ld;  // column stride
   const T *G = panels + d.panel_off + (int64_t)min(c0, d.nc - 1) * m + (valid ? i : 0);
   const bool full = ncol == TC && t.r0 + kFR <= d.m && (t.r0 >= d.nc || t.r0 + 1 >= c0 + TC);
-  T g[TC];
-  if (full) {
+  // a row's TC panel values are held in registers at once, except for FP64
+  // panels in grouped tiles (larger workgroups leave a thread fewer
+  // registers: 128 with 16 wavefronts): there the row is taken in chunks of
+  // TC / 2 (2 groups) or TC / 4 columns (4 groups), each loaded after the
+  // previous one's products
+  constexpr int TH = sizeof(T) == 8 && NG > 2 ? TC / 4 : sizeof(T) == 8 && NG > 1 ? TC / 2 : TC;
+  T g[TH];
+  auto load_chunk = [&](int j0) {
+    if (full) {
 #pragma unroll
-    for (int j = 0; j < TC; ++j) g[j] = panel_load<NT>(G + j * m);
-  } else {
+      for (int j = 0; j < TH; ++j) g[j] = panel_load<NT>(G + (j0 + j) * m);
+    } else {
 #pragma unroll
-    for (int j = 0; j < TC; ++j) g[j] = j < lim ? panel_load<NT>(G + j * m) : T(0);
-  }
+      for (int j = 0; j < TH; ++j) g[j] = j0 + j < lim ? panel_load<NT>(G + (j0 + j) * m) : T(0);
+    }
+  };
+  load_chunk(0);
   if (r < TC) s_in[grp][r] = r < ncol ? w[din] : T(0);
   __syncthreads();
   T acc = T(0);
-  if (lim > 0) {
-    T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
+#pragma unroll 1
+  for (int h = 0; h < TC / TH; ++h) {
+    if (h > 0) load_chunk(h * TH);
+    if (lim > h * TH) {
+      const T *x = s_in[grp] + h * TH;
+      T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-    for (int j = 0; j < TC; j += 4) {
-      a0 += g[j] * s_in[grp][j];
-      a1 += g[j + 1] * s_in[grp][j + 1];
-      a2 += g[j + 2] * s_in[grp][j + 2];
-      a3 += g[j + 3] * s_in[grp][j + 3];
+      for (int j = 0; j < TH; j += 4) {
+        a0 += g[j] * x[j];
+        a1 += g[j + 1] * x[j + 1];
+        a2 += g[j + 2] * x[j + 2];
+        a3 += g[j + 3] * x[j + 3];
+      }
+      acc += (a0 + a1) + (a2 + a3);
     }
-    acc = (a0 + a1) + (a2 + a3);
   }
   if constexpr (NG > 1) {
     // the groups' partial sums of a row meet in group 0 (fixed order), so a

@@ -180,6 +180,8 @@ def _recorded_traffic(workload, symbol):
     import hashlib
     try:
         rec = json.load(open(_traffic_record(workload)))
+        if sorted(rec["sources_sha256"]) != sorted(TRAFFIC_SOURCES):
+            return None
         for path, digest in rec["sources_sha256"].items():
             if hashlib.sha256(open(os.path.join(ROOT, path), "rb").read()).hexdigest() != digest:
                 return None
@@ -764,6 +766,57 @@ def _cpu_baseline_child(mode):
     print(json.dumps(out))
 
 
+# sources whose change invalidates a recorded traffic figure: the sweep and
+# SpMV kernels, and the analysis that lays out the sweep tiles
+TRAFFIC_SOURCES = ("paper_2306_05893_amd/csrc/kernels_solve.hip",
+                   "paper_2306_05893_amd/csrc/host_analyse.cpp")
+
+
+def _write_traffic_record(fetch_csv, write_csv, workload, copy_mib):
+    """Machine-readable HBM traffic of the SpMV and sweep kernels from two
+    rocprofv3 counter runs of the kernel pass (FETCH_SIZE, then WRITE_SIZE,
+    KiB per dispatch, with --calibrate-copy-mib): each counter is scaled by
+    what it reads for the calibration copy of known size, and the sweeps are
+    averaged per family over all their level launches (host only)."""
+    import csv
+    import hashlib
+    import re
+
+    def load(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            nm = re.sub(r"^void ", "", r["Kernel_Name"]).replace("fe::(anonymous namespace)::", "")
+            nm = nm[:nm.index("(")] if "(" in nm else nm
+            if nm.startswith("k_tri_fwd") or nm.startswith("k_tri_bwd"):
+                nm = nm[:len("k_tri_fwd")]
+            acc.setdefault(nm, []).append(float(r["Counter_Value"]))
+        return acc
+
+    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    cal = [k for k in f if "elementwise" in k]
+    if len(cal) != 1:
+        raise SystemExit("the counter runs need exactly one calibration copy kernel")
+    kib = copy_mib * 1024.0
+    fs = kib / (sum(f[cal[0]]) / len(f[cal[0]]))
+    ws = kib / (sum(w[cal[0]]) / len(w[cal[0]]))
+    rec = {"workload": f"{workload} mixed (bench.py --kernel-pass-only --workload {workload} "
+                       f"--kernel-applies 3 --calibrate-copy-mib {copy_mib})",
+           "sources_sha256": {p: hashlib.sha256(open(os.path.join(ROOT, p), "rb").read())
+                              .hexdigest() for p in TRAFFIC_SOURCES},
+           "fetch_scale": fs, "write_scale": ws, "kernels": {}}
+    for k in (KERNEL_SYMBOL["spmv"], KERNEL_SYMBOL["trisolve_fwd"], KERNEL_SYMBOL["trisolve_bwd"]):
+        fb = sum(f[k]) / len(f[k]) * 1024 * fs
+        wb = sum(w[k]) / len(w[k]) * 1024 * ws
+        rec["kernels"][k] = {"dispatches": len(f[k]), "fetch_bytes_per_launch": fb,
+                             "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb}
+    with open(_traffic_record(workload), "w") as out:
+        json.dump(rec, out, indent=1)
+    print(json.dumps({k: round(v["traffic_bytes_per_launch"] / 1e6, 1)
+                      for k, v in rec["kernels"].items()}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -798,7 +851,14 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (read + write), the "
                          "reference dispatch for scaling hardware byte counters")
+    ap.add_argument("--traffic-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="only write the traffic record of --workload from the counter "
+                         "collections of two rocprofv3 runs of the kernel pass (FETCH_SIZE, "
+                         "then WRITE_SIZE, both with --calibrate-copy-mib 1024); no GPU")
     args = ap.parse_args()
+    if args.traffic_record:
+        _write_traffic_record(args.traffic_record[0], args.traffic_record[1], args.workload, 1024)
+        return
     if args.cpu_baseline_child:
         _cpu_baseline_child(args.cpu_baseline_child)
         return

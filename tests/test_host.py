@@ -229,3 +229,45 @@ def test_bench_refuses_more_than_one_gpu():
         assert p.returncode == 2, (extra, p.stderr[-300:])
         assert "one GPU only" in p.stderr
         assert p.stdout == ""
+
+
+def test_traffic_record_scaling_and_sweep_families(tmp_path, monkeypatch):
+    """The traffic record scales each counter by what it reads for the 1 GiB
+    calibration copy, averages a sweep family over all its level launches
+    (whatever their tile template arguments) and is honoured only while the
+    kernel and tile-schedule sources are unchanged."""
+    import csv
+    import importlib
+    import json
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    bench = importlib.import_module("bench")
+    rec_path = tmp_path / "rec.txt"
+    monkeypatch.setattr(bench, "_traffic_record", lambda wl: str(rec_path))
+    ns = "void fe::(anonymous namespace)::"
+    # (kernel, FETCH_SIZE KiB, WRITE_SIZE KiB) per dispatch: the copy reads
+    # half its bytes on FETCH_SIZE (scale 2) and all of them on WRITE_SIZE
+    disp = [("void at::native::vectorized_elementwise_kernel<4>(int)", 524288.0, 1048576.0),
+            (ns + "k_spmv<float, 16>(long, int const*)", 100.0, 10.0),
+            (ns + "k_tri_fwd<float, 64, true, 1>(fe::TileDev const*)", 300.0, 6.0),
+            (ns + "k_tri_fwd<float, 64, true, 4>(fe::TileDev const*)", 500.0, 2.0),
+            (ns + "k_tri_bwd<float, 512, true, 16>(fe::TileDev const*)", 400.0, 4.0)]
+    for name, col in (("fetch.csv", 1), ("write.csv", 2)):
+        with open(tmp_path / name, "w", newline="") as fh:
+            wr = csv.writer(fh)
+            wr.writerow(["Kernel_Name", "Counter_Name", "Counter_Value"])
+            for d in disp:
+                wr.writerow([d[0], "FETCH_SIZE" if col == 1 else "WRITE_SIZE", d[col]])
+    bench._write_traffic_record(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"),
+                                "hex_block", 1024)
+    rec = json.load(open(rec_path))
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    fwd = rec["kernels"]["k_tri_fwd"]
+    assert fwd["dispatches"] == 2
+    assert fwd["traffic_bytes_per_launch"] == (400.0 * 2 + 4.0) * 1024
+    assert rec["kernels"]["k_spmv<float, 16>"]["traffic_bytes_per_launch"] == (200.0 + 10.0) * 1024
+    assert bench._recorded_traffic("hex_block", "k_tri_bwd") == round((800.0 + 4.0) * 1024)
+    rec["sources_sha256"][bench.TRAFFIC_SOURCES[1]] = "0" * 64  # a changed tile schedule
+    json.dump(rec, open(rec_path, "w"))
+    assert bench._recorded_traffic("hex_block", "k_tri_bwd") is None

@@ -155,26 +155,31 @@ struct Dissector {
 // cut into pieces (multiples of the 16-wide staging chunk, at least 64 long)
 // until it has about 512 tiles.
 // Sweep tile extents of one level where the caller left them to the
-// analysis (0).  Forward: a level whose supernodes mostly have 65..128 own
-// columns takes 128-column tiles, one per row block instead of two 64-column
-// tiles whose second is mostly empty, which halves the level's tiles, input
-// gathers and output atomics; other levels keep 64 (128 doubles the panel
-// registers of a thread and so halves the tiles in flight).  A level of wide
-// supernodes (256-column tiles pad its own columns by at most 10 % more than
-// 64-column ones, and it keeps kSweepMinTiles tiles) takes 4 groups of 64
-// columns per tile, whose row sums meet in one atomic per row: a quarter of
-// the atomics (forward levels 8-12 of the hex block 3-4 % faster; on narrow
-// supernodes the empty groups only cost).  Backward rows: 256-row tiles where they cover
-// the level's panel rows with clearly less padding than 512-row tiles
-// (supernodes of a few hundred rows), else 512.  Backward columns: the widest
-// of 64 and 32 (16 and 8 wavefronts sharing the tile's gathered inputs) that
-// pads the level's own columns by at most 5 % more than 32 does and still
-// gives the level kSweepMinTiles workgroups (4 per compute unit), else 16:
-// a small level is bound by the latency of its tiles, and fewer, wider tiles
-// only lengthen it (the 14,883-DOF beam ran 6 % slower with them).  On the
-// 1.39 M-DOF hex block: forward levels 2 and 3 100 -> 81 and 79 -> 67 us,
-// backward level 2 113 -> 93 us; the backward sweep 2.22 -> 2.02 ms with
-// 32-column instead of 16-column tiles, and about 0.03 ms less with 64
+// analysis (0).
+//  * Forward columns: a level whose supernodes mostly have 65..128 own
+//    columns takes 128-column tiles, one per row block instead of two
+//    64-column tiles whose second is mostly empty, which halves the level's
+//    tiles, input gathers and output atomics; other levels keep 64 (128
+//    doubles the panel registers of a thread and so halves the tiles in
+//    flight).
+//  * Forward column groups: a level of wide supernodes (256-column tiles pad
+//    its own columns by at most 10 % more than 64-column ones, and it keeps
+//    kSweepMinTiles tiles) takes 4 groups of 64 columns per tile, whose row
+//    sums meet in one atomic per row: a quarter of the atomics (forward
+//    levels 8-12 of the hex block 3-4 % faster; on narrow supernodes the
+//    empty groups only cost).
+//  * Backward rows: 256-row tiles where they cover the level's panel rows
+//    with clearly less padding than 512-row tiles (supernodes of a few
+//    hundred rows), else 512.
+//  * Backward columns: the widest of 64 and 32 (16 and 8 wavefronts sharing
+//    the tile's gathered inputs) that pads the level's own columns by at
+//    most 5 % more than 32 does and still gives the level kSweepMinTiles
+//    workgroups (4 per compute unit), else 16: a small level is bound by the
+//    latency of its tiles, and fewer, wider tiles only lengthen it (the
+//    14,883-DOF beam ran 6 % slower with them).
+// On the 1.39 M-DOF hex block: forward levels 2 and 3 100 -> 81 and 79 ->
+// 67 us, backward level 2 113 -> 93 us; the backward sweep 2.22 -> 2.02 ms
+// with 32-column instead of 16-column tiles, and about 0.03 ms less with 64
 // columns on its wide levels.
 constexpr double kSweepMinTiles = 1024;
 static void tile_extents_for_level(const Symbolic &S, const std::vector<int32_t> &sns,

@@ -247,6 +247,21 @@ int fe_export_ordering(fe_ctx *ctx, int32_t *perm, int32_t *sn_ptr);
  * launch per level).  Either pointer may be NULL.  Host work only. */
 int fe_export_supernodes(fe_ctx *ctx, int32_t *n_rows, int32_t *level);
 
+/* Export the triangular sweeps' tile schedule (Sec. 5.1: the level-scheduled
+ * solve of the regional problems), for diagnostics and tests.  Counts:
+ * *n_levels, *n_fwd, *n_bwd (any may be NULL).  extents (host [n_levels * 4]
+ * or NULL): per level, the forward tile width in columns per group, the
+ * forward column groups, the backward tile height and width.  fwd / bwd
+ * (host [n_fwd * 3] / [n_bwd * 3] or NULL): per tile, in launch order
+ * (forward: levels ascending; backward: descending), its supernode, first
+ * panel row r0 and first own column c0.  A forward tile covers rows r0 ..
+ * r0 + 255 and columns c0 .. c0 + width * groups - 1, a backward tile rows
+ * r0 .. r0 + height - 1 and columns c0 .. c0 + width - 1, clipped to the
+ * supernode's panel; only entries on or below the diagonal of L11^{-1} are
+ * read.  Host work only. */
+int fe_export_sweep_tiles(fe_ctx *ctx, int32_t *n_levels, int32_t *n_fwd, int32_t *n_bwd,
+                          int32_t *extents, int32_t *fwd, int32_t *bwd);
+
 /* Assemble A (CSR values, FP32 for FE_PREC_MIXED / FP64 for FE_PREC_FP64,
  * device [nnz]) and b (FP64 device [n_dofs]) at state (q, v) (device [n_dofs]
  * each):  A = (1 + h alpha) M + h (beta + h) K(q),

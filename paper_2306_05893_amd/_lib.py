@@ -89,6 +89,7 @@ SIGNATURES = {
     "fe_export_pattern": (C.c_int, [_P, _P, _P, _P]),
     "fe_export_ordering": (C.c_int, [_P, _P, _P]),
     "fe_export_supernodes": (C.c_int, [_P, _P, _P]),
+    "fe_export_sweep_tiles": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "fe_assemble": (C.c_int, [_P, C.POINTER(fe_params), _P, _P, _P, _P, _P]),
     "fe_factor_async": (C.c_int, [_P, _P, C.c_int64, _P]),
     "fe_factor_status": (C.c_int, [_P, C.POINTER(C.c_int64)]),

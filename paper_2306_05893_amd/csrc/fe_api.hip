@@ -1450,6 +1450,33 @@ int fe_export_supernodes(fe_ctx *c, int32_t *n_rows, int32_t *level) {
   return FE_OK;
 }
 
+int fe_export_sweep_tiles(fe_ctx *c, int32_t *n_levels, int32_t *n_fwd, int32_t *n_bwd,
+                          int32_t *extents, int32_t *fwd, int32_t *bwd) {
+  if (!c) return FE_EINVAL;
+  const Symbolic &S = c->S;
+  if (n_levels) *n_levels = S.n_levels;
+  if (n_fwd) *n_fwd = (int32_t)S.fwd_tiles.size();
+  if (n_bwd) *n_bwd = (int32_t)S.bwd_tiles.size();
+  if (extents)
+    for (int L = 0; L < S.n_levels; ++L) {
+      extents[4 * L + 0] = S.fwd_level_cols[L];
+      extents[4 * L + 1] = S.fwd_level_groups[L];
+      extents[4 * L + 2] = S.bwd_level_rows[L];
+      extents[4 * L + 3] = S.bwd_level_cols[L];
+    }
+  auto put = [](const std::vector<Tile> &tl, int32_t *out) {
+    if (!out) return;
+    for (size_t i = 0; i < tl.size(); ++i) {
+      out[3 * i + 0] = tl[i].s;
+      out[3 * i + 1] = tl[i].r0;
+      out[3 * i + 2] = tl[i].c0;
+    }
+  };
+  put(S.fwd_tiles, fwd);
+  put(S.bwd_tiles, bwd);
+  return FE_OK;
+}
+
 int fe_assemble(fe_ctx *c, const fe_params *params, const double *q, const double *v,
                 void *A_vals, double *b, void *stream) {
   if (!c) return FE_EINVAL;

@@ -207,6 +207,22 @@ class FEContext:
                                                 lev.ctypes.data_as(C.c_void_p)))
         return m, lev
 
+    def export_sweep_tiles(self):
+        """The sweeps' tile schedule: per-level extents [n_levels, 4] (forward
+        width, forward groups, backward height, backward width) and the
+        forward and backward tiles [n, 3] (supernode, r0, c0) in launch order."""
+        nl, nf, nb = C.c_int32(), C.c_int32(), C.c_int32()
+        self._chk(self.lib.fe_export_sweep_tiles(self.h, C.byref(nl), C.byref(nf), C.byref(nb),
+                                                 None, None, None))
+        ext = np.empty((nl.value, 4), dtype=np.int32)
+        fwd = np.empty((nf.value, 3), dtype=np.int32)
+        bwd = np.empty((nb.value, 3), dtype=np.int32)
+        self._chk(self.lib.fe_export_sweep_tiles(self.h, None, None, None,
+                                                 ext.ctypes.data_as(C.c_void_p),
+                                                 fwd.ctypes.data_as(C.c_void_p),
+                                                 bwd.ctypes.data_as(C.c_void_p)))
+        return ext, fwd, bwd
+
     def host_factor_apply(self, A_host, r_host):
         """Host-only: factor FP64 CSR values and apply P^{-1} to rows of r."""
         A = np.ascontiguousarray(A_host, dtype=np.float64)

@@ -271,3 +271,41 @@ def test_traffic_record_scaling_and_sweep_families(tmp_path, monkeypatch):
     rec["sources_sha256"][bench.TRAFFIC_SOURCES[1]] = "0" * 64  # a changed tile schedule
     json.dump(rec, open(rec_path, "w"))
     assert bench._recorded_traffic("hex_block", "k_tri_bwd") is None
+
+
+@pytest.mark.parametrize("mesh", ["hex_diff", "hex_beam"])
+@pytest.mark.parametrize("opts", [{}, {"fwd_tile_cols": 64, "fwd_col_groups": 4,
+                                       "bwd_tile_rows": 1024, "bwd_tile_cols": 64},
+                                  {"fwd_tile_cols": 128, "bwd_tile_rows": 256,
+                                   "bwd_tile_cols": 16}])
+def test_sweep_tiles_cover_each_lower_panel_entry_once(mesh, opts):
+    """The sweeps' tile schedule (per-level extents chosen by the analysis, or
+    fixed by the build options) covers every panel entry on or below the
+    diagonal of L11^{-1} exactly once in each sweep, with tiles in level order
+    (forward ascending, backward descending)."""
+    w = synth.make(mesh)
+    ctx = FEContext(w.X, w.conn, w.elem_type, w.fixed, prec=1, device="cpu", **opts)
+    _, snp = ctx.export_ordering()
+    m, lev = ctx.export_supernodes()
+    nc = np.diff(snp)
+    ext, fwd, bwd = ctx.export_sweep_tiles()
+    assert ext.shape == (int(lev.max()) + 1, 4)
+    assert set(ext[:, 0]) <= {16, 32, 64, 128} and set(ext[:, 1]) <= {1, 2, 4}
+    assert set(ext[:, 2]) <= {256, 512, 1024} and set(ext[:, 3]) <= {16, 32, 64}
+    assert all(g == 1 or c == 64 for c, g in ext[:, :2])
+    for key, val in opts.items():  # a fixed extent holds on every level it applies to
+        col = {"fwd_tile_cols": 0, "fwd_col_groups": 1, "bwd_tile_rows": 2, "bwd_tile_cols": 3}[key]
+        assert (ext[:, col] == val).all() or (key == "fwd_col_groups" and
+                                              (ext[ext[:, 0] == 64, 1] == val).all())
+    for tiles, fwd_dir in ((fwd, True), (bwd, False)):
+        tl = lev[tiles[:, 0]]
+        assert (np.diff(tl) >= 0).all() if fwd_dir else (np.diff(tl) <= 0).all()
+        cover = [np.zeros((int(m[s]), int(nc[s])), dtype=np.int32) for s in range(len(m))]
+        for s, r0, c0 in tiles:
+            L = lev[s]
+            h = 256 if fwd_dir else ext[L, 2]
+            wdt = ext[L, 0] * ext[L, 1] if fwd_dir else ext[L, 3]
+            cover[s][r0:r0 + h, c0:c0 + wdt] += 1
+        for s in range(len(m)):
+            low = np.tril(np.ones((int(m[s]), int(nc[s])), dtype=bool))
+            assert (cover[s][low] == 1).all(), (mesh, s, fwd_dir)

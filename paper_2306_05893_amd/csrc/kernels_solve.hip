@@ -281,13 +281,15 @@ __global__ void k_tri_prep(int64_t n, const double *r, T *w, T *y, double *z,
   z[i] = fixed[i] ? ri : 0.0;
 }
 
-constexpr int kFR = 256;  // forward tile: 256 rows x TC columns (TC: 16..128)
+constexpr int kFR = 256;  // forward tile: 256 rows x NG groups of TC columns (TC: 16..128)
 // backward tile: 4 NW columns x BR rows (BR: 256..1024), NW wavefronts of 4 columns
 
 // Forward tile: t[i] = sum_{j in tile cols} G[i, j] w[rows[j]] for the tile's
-// rows (one row per thread, consecutive rows = consecutive addresses of the
-// column-major panel); own rows (i < nc) accumulate into y, struct rows
-// subtract from w.  Entries above the diagonal of L11^{-1} are skipped.
+// rows (one row per thread of each group of 4 wavefronts, consecutive rows =
+// consecutive addresses of the column-major panel; NG groups take NG runs of
+// TC columns and meet in one sum per row); own rows (i < nc) accumulate into
+// y, struct rows subtract from w.  Entries above the diagonal of L11^{-1}
+// are skipped.
 // All TC panel loads of a row are issued before the gather of the inputs
 // w[rows[j]] (an index load and a dependent load), so one tile costs about
 // three memory latencies instead of one per group of columns.  With NT the
